@@ -1,0 +1,48 @@
+"""Synthetic inputs: determinism and canonical CSR form."""
+import numpy as np
+
+from synth import make_workload, arrival_trace
+
+
+def _canonical(c, v):
+    assert c.rowptr.dtype == np.int64 and c.col.dtype == np.int32 and c.val.dtype == np.float32
+    assert c.rowptr[0] == 0 and np.all(np.diff(c.rowptr) > 0)
+    assert c.col.min() >= 0 and c.col.max() < v
+    assert np.all(c.val > 0) and np.all(np.isfinite(c.val))
+    for r in range(c.n):
+        cc, vv = c.row(r)
+        assert np.all(np.diff(cc) > 0)
+        assert abs(float(vv.astype(np.float64).sum()) - 1.0) < 1e-5
+
+
+def test_tiny_is_deterministic_and_canonical():
+    a = make_workload("tiny")
+    b = make_workload("tiny")
+    assert np.array_equal(a.V, b.V)
+    for x, y in ((a.db, b.db), (a.queries, b.queries)):
+        assert np.array_equal(x.rowptr, y.rowptr) and np.array_equal(x.col, y.col)
+        assert np.array_equal(x.val, y.val)
+    _canonical(a.db, a.V.shape[0])
+    _canonical(a.queries, a.V.shape[0])
+    assert a.db.n == 200 and a.queries.n == 8 and a.V.shape == (2000, 64)
+    L = a.db.lengths()
+    assert L.min() >= 10 and L.max() <= 40
+
+
+def test_text_and_image_shapes_small():
+    t = make_workload("text", n=300, B=20, v=5000)
+    _canonical(t.db, 5000)
+    L = t.db.lengths()
+    assert L.min() >= 50 and L.max() <= 300 and 90 < L.mean() < 150
+    assert np.allclose(np.linalg.norm(t.V.astype(np.float64), axis=1), 1.0, atol=1e-6)
+    im = make_workload("image", n=500, B=10)
+    _canonical(im.db, 784)
+    assert im.V.shape == (784, 2) and np.all(im.V == np.round(im.V))
+    assert 100 < im.db.lengths().mean() < 220
+
+
+def test_arrival_trace():
+    t, q = arrival_trace(1000.0, 200, 5000)
+    assert np.all(np.diff(t) > 0) and q.n == 200
+    L = q.lengths()
+    assert L.min() >= 10 and L.max() <= 500
