@@ -1,0 +1,245 @@
+/*
+ * lcemd: linear-complexity lower bounds of the Earth Mover's Distance on one
+ * MI355X (gfx950), after Atasu & Mittelholzer, "Low-Complexity Data-Parallel
+ * Earth Mover's Distance Approximations" (ICML 2019).
+ *
+ * Problem (Sec. 2.2 and Sec. 4): a vocabulary of v words with m-dimensional
+ * embeddings V (v x m), a database X of n histograms over that vocabulary
+ * (sparse rows, weights summing to 1), and a batch of B query histograms over
+ * the same vocabulary.  For every (query, database histogram) pair the
+ * library computes a lower bound of the EMD with Euclidean ground cost
+ * (Sec. 5):
+ *
+ *   RWMD  one-sided relaxed WMD (Sec. 2.1); equal to ACT with k = 1
+ *   OMR   overlapping mass reduction (Alg. 1)
+ *   ACT   approximate iterative constrained transfers, k >= 1 (Alg. 3)
+ *   ICT   iterative constrained transfers (Alg. 2)
+ *
+ * in direction D2Q (move the database histogram into the query: the LC
+ * direction of Sec. 4), Q2D (move the query into the database histogram) or
+ * SYM (the maximum of the two, Sec. 2.1 and Sec. 5), and returns either the
+ * full B x n distance matrix or the l nearest database histograms per query
+ * (Sec. 5, top-l search).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Return value: LCEMD_OK (0) on success, a negative LCEMD_E_* code on
+ *   failure; lcemd_last_error() then describes the failure.  No C++
+ *   exception crosses this interface.  On failure, caller-owned outputs are
+ *   left untouched unless the failure is LCEMD_E_HIP (a device error after
+ *   work was issued).
+ * - Validation of every argument (shapes, CSR structure, weights) happens
+ *   before any device work is issued.
+ * - Histograms are CSR: rowptr (int64, rows+1, rowptr[0] == 0,
+ *   non-decreasing, no empty rows), col (int32 word ids in [0, v), strictly
+ *   increasing within a row), val (float32, finite and > 0, each row sums to
+ *   1 within 1e-5).  Explicit zeros are rejected: a zero-weight bin would take
+ *   a top-k slot in Alg. 3.
+ * - Pointer residency: without LCEMD_PTR_DEVICE every array argument is host
+ *   memory and every call returns with its outputs complete.  With
+ *   LCEMD_PTR_DEVICE every array argument of that call (inputs and outputs)
+ *   is device memory on the context's device; outputs are then ordered on
+ *   the context's stream.
+ * - Ownership: loads copy into library-owned device memory (the caller may
+ *   free its arrays on return); queries and outputs stay caller-owned.
+ * - A context is not thread-safe; calls on one context must be serialised.
+ */
+#ifndef LCEMD_H
+#define LCEMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LCEMD_VERSION 1
+
+/* status codes */
+#define LCEMD_OK 0
+#define LCEMD_E_INVALID_ARG (-1) /* bad scalar argument or NULL pointer */
+#define LCEMD_E_BAD_CSR (-2)     /* malformed histogram CSR or weights */
+#define LCEMD_E_NOT_LOADED (-3)  /* embeddings or database not loaded yet */
+#define LCEMD_E_OOM (-4)         /* device allocation failed */
+#define LCEMD_E_HIP (-5)         /* HIP runtime / kernel launch failure */
+#define LCEMD_E_UNSUPPORTED (-6) /* option combination not implemented */
+#define LCEMD_E_CAPACITY (-7)    /* a size exceeds a documented limit */
+#define LCEMD_E_NO_DEVICE (-8)   /* no usable GPU */
+
+/* distance measures */
+#define LCEMD_RWMD 0
+#define LCEMD_OMR 1
+#define LCEMD_ACT 2
+#define LCEMD_ICT 3
+
+/* directions */
+#define LCEMD_D2Q 0
+#define LCEMD_Q2D 1
+#define LCEMD_SYM 2
+
+/* arithmetic of the phase-1 distance contraction (candidate selection);
+ * the selected candidates' distances are always recomputed exactly in
+ * float32 from the float32 embeddings */
+#define LCEMD_FP32 0
+#define LCEMD_BF16 1
+#define LCEMD_FP8 2
+
+/* flags */
+#define LCEMD_PTR_DEVICE 0x1u  /* array arguments are device pointers */
+#define LCEMD_NORMALIZE 0x2u   /* load_database: renormalise rows (float64 sums) */
+#define LCEMD_L2_NORMALIZE 0x4u /* load_embeddings: scale rows to unit L2 norm */
+
+/* limits */
+#define LCEMD_MAX_HIST 512  /* max non-zeros of one query or database row */
+#define LCEMD_MAX_L 1024    /* max l of lcemd_topl */
+#define LCEMD_MAX_K 512     /* max k of ACT */
+
+typedef struct lcemd_ctx lcemd_ctx;
+
+typedef struct {
+  const int64_t* rowptr; /* B+1 row pointers */
+  const int32_t* col;    /* word ids */
+  const float* val;      /* weights */
+  int64_t B;             /* number of queries, >= 1 */
+  uint32_t flags;        /* LCEMD_PTR_DEVICE: rowptr/col/val and the call's
+                            outputs are device pointers */
+} lcemd_query;
+
+typedef struct {
+  int32_t method;       /* LCEMD_RWMD / OMR / ACT / ICT */
+  int32_t k;            /* ACT only: 1 <= k <= LCEMD_MAX_K; ignored otherwise */
+  int32_t direction;    /* LCEMD_D2Q / Q2D / SYM */
+  int32_t precision;    /* LCEMD_FP32 / BF16 / FP8 */
+  int32_t exclude_self; /* lcemd_topl: if >= 0, query b never returns
+                           database row (exclude_self + b) (self-join use) */
+  int32_t reserved[3];  /* must be 0 */
+} lcemd_opts;
+
+/* Library version (LCEMD_VERSION). */
+int lcemd_version(void);
+
+/* Create a context on HIP device `device` (its own default-priority stream
+ * until lcemd_set_stream).  *out receives the context.  Errors:
+ * LCEMD_E_NO_DEVICE if the device does not exist or is not gfx950,
+ * LCEMD_E_INVALID_ARG if out is NULL. */
+int lcemd_create(lcemd_ctx** out, int device);
+
+/* Free all library-owned device memory and the context.  NULL-safe. */
+void lcemd_destroy(lcemd_ctx* ctx);
+
+/* Issue all further work of this context on `hip_stream` (a hipStream_t,
+ * NULL = the library's own stream).  The caller keeps ownership. */
+int lcemd_set_stream(lcemd_ctx* ctx, void* hip_stream);
+
+/* Message of the last failing call on this context (context-owned string;
+ * "" if none).  Also valid for ctx == NULL (then: last lcemd_create error). */
+const char* lcemd_last_error(const lcemd_ctx* ctx);
+
+/* Load the vocabulary embeddings V: v rows of m float32 (row-major, finite),
+ * the coordinates of Sec. 4's matrix V.  Replaces earlier embeddings (and
+ * drops a loaded database).  Builds the device-side padded copy, the row
+ * norms (accumulated in float64) and, on request at query time, bfloat16 /
+ * fp8 copies.  Flags: LCEMD_PTR_DEVICE, LCEMD_L2_NORMALIZE.
+ * Limits: 1 <= v < 2^31, 1 <= m <= 4096. */
+int lcemd_load_embeddings(lcemd_ctx* ctx, const float* V, int64_t v, int32_t m,
+                          uint32_t flags);
+
+/* Load the database X (Sec. 4: n histograms over the vocabulary, kept in
+ * CSR).  Requires embeddings.  Derives the used vocabulary (the union of
+ * the database's words, Sec. 2.2) and, per used word, the largest weight
+ * any database row gives it (bounds how deep a transfer can go).  Flags:
+ * LCEMD_PTR_DEVICE, LCEMD_NORMALIZE.  Limits: n >= 1, at most
+ * LCEMD_MAX_HIST non-zeros per row. */
+int lcemd_load_database(lcemd_ctx* ctx, const int64_t* rowptr, const int32_t* col,
+                        const float* val, int64_t n, uint32_t flags);
+
+/* All B x n distances (row-major float32, out[b*n + u]) between the query
+ * batch and the database for one measure and direction (Sec. 2.1, Alg. 1-3,
+ * Sec. 4).  Queries: at most LCEMD_MAX_HIST words each. */
+int lcemd_distances(lcemd_ctx* ctx, const lcemd_query* q, const lcemd_opts* o,
+                    float* out);
+
+/* The l nearest database rows per query (Sec. 5 top-l search), ascending by
+ * (distance, database row index): idx[b*l + r] (int64) and dist[b*l + r]
+ * (float32).  1 <= l <= min(n, LCEMD_MAX_L).  SYM is evaluated exactly with
+ * lower-bound pruning: SYM >= D2Q, so only rows whose D2Q value can still
+ * enter the result get a Q2D evaluation. */
+int lcemd_topl(lcemd_ctx* ctx, const lcemd_query* q, const lcemd_opts* o,
+               int32_t l, int64_t* idx, float* dist);
+
+/* Phase-1 tables of Sec. 4 for every query and every used vocabulary word
+ * (used words in ascending word id order; lcemd_used_vocab lists them):
+ * S = positions (0-based, within the query row) of the k_eff = min(k, h_b)
+ * nearest query words, ascending by (distance, position); Z = their
+ * distances; W = their query weights.  Layout [b][used word][k]; entries
+ * l >= k_eff hold S = -1, Z = 0, W = 0.  Uses o->k and o->precision; method
+ * and direction are ignored.  Meant for verification: B x used x k entries. */
+int lcemd_tables(lcemd_ctx* ctx, const lcemd_query* q, const lcemd_opts* o,
+                 int32_t* S, float* Z, float* W);
+
+/* Host-only check (no device needed) that `rows` histograms in host memory
+ * follow the CSR conventions above over a vocabulary of v words, with row
+ * sums checked when require_normalized != 0.  Returns LCEMD_OK,
+ * LCEMD_E_BAD_CSR, LCEMD_E_CAPACITY or LCEMD_E_INVALID_ARG; a description of
+ * the first violation is written to msg (msg_cap bytes, may be NULL).  The
+ * same check guards every call that takes histograms. */
+int lcemd_check_histograms(const int64_t* rowptr, const int32_t* col, const float* val,
+                           int64_t rows, int64_t v, int require_normalized, char* msg,
+                           size_t msg_cap);
+
+/* Number of used vocabulary words (after lcemd_load_database); if ids is
+ * non-NULL also writes them (host int32, ascending). */
+int64_t lcemd_used_vocab(lcemd_ctx* ctx, int32_t* ids);
+
+/* Per-kernel timing of the most recent lcemd_distances / lcemd_topl call
+ * when enabled: device time measured with HIP events on the context's
+ * stream.  lcemd_profile(ctx, 1) enables recording; lcemd_profile_get fills
+ * up to `cap` entries and returns how many there are. */
+typedef struct {
+  char name[48];     /* kernel / phase name */
+  double ms;         /* summed device time of its launches in the call */
+  int64_t launches;  /* launches in the call */
+  double work;       /* algorithmic units processed (bytes or flops) */
+} lcemd_phase_time;
+int lcemd_profile(lcemd_ctx* ctx, int enable);
+int lcemd_profile_get(lcemd_ctx* ctx, lcemd_phase_time* out, int cap);
+
+/* ---------------------------------------------------------------------
+ * Serving: continuous batching of a query stream against the resident
+ * database.  Submitted queries wait in an admission queue; a worker thread
+ * admits them into free slots while their device memory fits the budget,
+ * runs their phase 1 as one batch and their phase 2 on a persistent kernel
+ * fed by a device work queue, and completes each query independently.
+ * Results do not depend on which other queries shared the device.
+ * --------------------------------------------------------------------- */
+typedef struct lcemd_server lcemd_server;
+
+typedef struct {
+  int32_t method;        /* as lcemd_opts */
+  int32_t k;
+  int32_t precision;
+  int32_t l;             /* neighbours returned per query */
+  int32_t max_slots;     /* queries in flight at once (>= 1) */
+  int32_t max_batch_words; /* words admitted into one phase-1 batch */
+  int64_t memory_budget; /* device bytes for in-flight query state */
+  int32_t use_graph;     /* capture the per-batch launches in a hipGraph */
+  int32_t reserved[5];
+} lcemd_server_cfg;
+
+int lcemd_server_start(lcemd_ctx* ctx, const lcemd_server_cfg* cfg, lcemd_server** out);
+/* Queue one query (host arrays, h words, canonical form).  *ticket gets
+ * its id.  LCEMD_E_CAPACITY if the query can never fit the budget. */
+int lcemd_server_submit(lcemd_server* s, const int32_t* col, const float* val, int32_t h,
+                        uint64_t* ticket);
+/* Block until `ticket` completes; writes l (idx, dist) pairs and the
+ * seconds from submit to completion. */
+int lcemd_server_wait(lcemd_server* s, uint64_t ticket, int64_t* idx, float* dist,
+                      double* latency_s);
+/* Drain and stop; frees the server.  NULL-safe. */
+void lcemd_server_stop(lcemd_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LCEMD_H */

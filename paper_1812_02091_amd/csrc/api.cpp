@@ -1,0 +1,832 @@
+// C-ABI entry points of lcemd (declared in include/lcemd.h): context and
+// resident memory, argument validation, and the launch sequence of the hot
+// path (Sec. 4 Phase 1 -> Phase 2/3 -> top-l of Sec. 5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace lcemd;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+  double work;
+};
+
+}  // namespace
+
+struct lcemd_ctx {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // embeddings (Sec. 4: V)
+  int64_t v = 0;
+  int m = 0, m_pad = 0;
+  float* V = nullptr;
+  float* vnorm = nullptr;
+  uint16_t* Vb = nullptr;
+  // database (Sec. 4: X in CSR)
+  int64_t n = 0, nnz = 0, v_used = 0;
+  int db_hmax = 0;
+  int64_t* xptr = nullptr;
+  int2* xcv = nullptr;
+  int32_t* xcol = nullptr;
+  int32_t* used = nullptr;
+  float* xmax = nullptr;
+  std::vector<int32_t> used_host;
+  // scratch, grow-only
+  std::map<std::string, DevBuf> ws;
+  size_t table_budget = size_t(12) << 30;
+  // profiling
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<lcemd_phase_time> last;
+};
+
+namespace {
+
+int fail(lcemd_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, LCEMD_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+void dfree(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+template <typename T>
+int dalloc(lcemd_ctx* c, T*& p, size_t count, const char* what) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, LCEMD_E_OOM, "device allocation of %zu bytes for %s failed",
+                count * sizeof(T), what);
+  }
+  p = static_cast<T*>(q);
+  return LCEMD_OK;
+}
+
+// grow-only named scratch buffer
+template <typename T>
+int wsget(lcemd_ctx* c, const char* name, size_t count, T*& out) {
+  DevBuf& b = c->ws[name];
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (b.bytes < bytes) {
+    if (b.p) {
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, LCEMD_E_OOM, "scratch allocation of %zu bytes (%s) failed", bytes, name);
+    }
+    b.bytes = bytes;
+  }
+  out = static_cast<T*>(b.p);
+  return LCEMD_OK;
+}
+
+void free_db(lcemd_ctx* c) {
+  dfree((void*&)c->xptr);
+  dfree((void*&)c->xcv);
+  dfree((void*&)c->xcol);
+  dfree((void*&)c->used);
+  dfree((void*&)c->xmax);
+  c->n = c->nnz = c->v_used = 0;
+  c->db_hmax = 0;
+  c->used_host.clear();
+}
+
+void free_emb(lcemd_ctx* c) {
+  dfree((void*&)c->V);
+  dfree((void*&)c->vnorm);
+  dfree((void*&)c->Vb);
+  c->v = 0;
+  c->m = c->m_pad = 0;
+}
+
+// ------------------------------- profiling --------------------------------
+void prof_reset(lcemd_ctx* c) {
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->recs.clear();
+}
+
+int prof_begin(lcemd_ctx* c, const char* name, double work) {
+  if (!c->prof) return LCEMD_OK;
+  ProfRec r;
+  r.name = name;
+  r.work = work;
+  HIPCHK(c, hipEventCreate(&r.a));
+  HIPCHK(c, hipEventCreate(&r.b));
+  HIPCHK(c, hipEventRecord(r.a, c->stream));
+  c->recs.push_back(r);
+  return LCEMD_OK;
+}
+
+int prof_end(lcemd_ctx* c) {
+  if (!c->prof || c->recs.empty()) return LCEMD_OK;
+  HIPCHK(c, hipEventRecord(c->recs.back().b, c->stream));
+  return LCEMD_OK;
+}
+
+int prof_collect(lcemd_ctx* c) {
+  c->last.clear();
+  if (!c->prof) return LCEMD_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::map<std::string, size_t> at;
+  for (auto& r : c->recs) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, r.a, r.b));
+    auto it = at.find(r.name);
+    if (it == at.end()) {
+      lcemd_phase_time t{};
+      snprintf(t.name, sizeof t.name, "%s", r.name.c_str());
+      at[r.name] = c->last.size();
+      c->last.push_back(t);
+      it = at.find(r.name);
+    }
+    lcemd_phase_time& t = c->last[it->second];
+    t.ms += ms;
+    t.launches += 1;
+    t.work += r.work;
+  }
+  prof_reset(c);
+  return LCEMD_OK;
+}
+
+// ------------------------------- validation -------------------------------
+// Host-side check of a CSR histogram batch; returns LCEMD_OK or
+// LCEMD_E_BAD_CSR with a message.  hmax receives the longest row.
+int check_csr_host(lcemd_ctx* c, const char* what, const int64_t* ptr, const int32_t* col,
+                   const float* val, int64_t rows, int64_t v, bool require_norm, int* hmax) {
+  if (ptr[0] != 0) return fail(c, LCEMD_E_BAD_CSR, "%s: rowptr[0] must be 0", what);
+  int hm = 0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const int64_t a = ptr[r], b = ptr[r + 1];
+    if (b <= a) return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld is empty or rowptr decreases", what, (long long)r);
+    if (b - a > LCEMD_MAX_HIST)
+      return fail(c, LCEMD_E_CAPACITY, "%s: row %lld has %lld non-zeros (limit %d)", what,
+                  (long long)r, (long long)(b - a), LCEMD_MAX_HIST);
+    hm = std::max<int>(hm, (int)(b - a));
+    double sum = 0.0;
+    int prev = -1;
+    for (int64_t i = a; i < b; ++i) {
+      if (col[i] <= prev || col[i] >= v)
+        return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld: column ids must be strictly increasing in [0, %lld)",
+                    what, (long long)r, (long long)v);
+      prev = col[i];
+      if (!(val[i] > 0.f) || !std::isfinite(val[i]))
+        return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld: weights must be finite and > 0", what, (long long)r);
+      sum += (double)val[i];
+    }
+    if (require_norm && std::fabs(sum - 1.0) > 1e-5)
+      return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld sums to %.9g, not 1", what, (long long)r, sum);
+  }
+  *hmax = hm;
+  return LCEMD_OK;
+}
+
+int check_ptr_host(lcemd_ctx* c, const char* what, const int64_t* ptr, int64_t rows, int* hmax) {
+  if (ptr[0] != 0) return fail(c, LCEMD_E_BAD_CSR, "%s: rowptr[0] must be 0", what);
+  int hm = 0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const int64_t d = ptr[r + 1] - ptr[r];
+    if (d <= 0) return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld is empty or rowptr decreases", what, (long long)r);
+    if (d > LCEMD_MAX_HIST)
+      return fail(c, LCEMD_E_CAPACITY, "%s: row %lld has %lld non-zeros (limit %d)", what,
+                  (long long)r, (long long)d, LCEMD_MAX_HIST);
+    hm = std::max<int>(hm, (int)d);
+  }
+  *hmax = hm;
+  return LCEMD_OK;
+}
+
+// Device-resident query: validated and (for host input) staged on device.
+struct QDev {
+  int64_t B = 0, nnz = 0;
+  const int64_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const float* val = nullptr;
+  std::vector<int64_t> hptr;
+  int hmax = 0;
+  bool device = false;
+};
+
+int stage_query(lcemd_ctx* c, const lcemd_query* q, QDev& Q) {
+  if (!q || !q->rowptr || !q->col || !q->val) return fail(c, LCEMD_E_INVALID_ARG, "query arrays must not be NULL");
+  if (q->B < 1) return fail(c, LCEMD_E_INVALID_ARG, "query batch must hold at least one histogram");
+  if (q->B > (int64_t(1) << 24)) return fail(c, LCEMD_E_CAPACITY, "query batch too large");
+  Q.B = q->B;
+  Q.device = (q->flags & LCEMD_PTR_DEVICE) != 0;
+  Q.hptr.resize(Q.B + 1);
+  if (!Q.device) {
+    memcpy(Q.hptr.data(), q->rowptr, sizeof(int64_t) * (Q.B + 1));
+    int rc = check_csr_host(c, "query", q->rowptr, q->col, q->val, Q.B, c->v, true, &Q.hmax);
+    if (rc) return rc;
+    Q.nnz = Q.hptr[Q.B];
+    int64_t* dp;
+    int32_t* dc;
+    float* dv;
+    if ((rc = wsget(c, "q_ptr", Q.B + 1, dp)) || (rc = wsget(c, "q_col", Q.nnz, dc)) ||
+        (rc = wsget(c, "q_val", Q.nnz, dv)))
+      return rc;
+    HIPCHK(c, hipMemcpyAsync(dp, q->rowptr, sizeof(int64_t) * (Q.B + 1), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dc, q->col, sizeof(int32_t) * Q.nnz, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dv, q->val, sizeof(float) * Q.nnz, hipMemcpyHostToDevice, c->stream));
+    Q.ptr = dp;
+    Q.col = dc;
+    Q.val = dv;
+  } else {
+    HIPCHK(c, hipMemcpyAsync(Q.hptr.data(), q->rowptr, sizeof(int64_t) * (Q.B + 1), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc = check_ptr_host(c, "query", Q.hptr.data(), Q.B, &Q.hmax);
+    if (rc) return rc;
+    Q.nnz = Q.hptr[Q.B];
+    int* derr;
+    if ((rc = wsget(c, "q_err", 1, derr))) return rc;
+    HIPCHK(c, hipMemsetAsync(derr, 0, sizeof(int), c->stream));
+    HIPCHK(c, launch_validate_csr(q->rowptr, q->col, q->val, Q.B, c->v, 1, derr, c->stream));
+    int herr = 0;
+    HIPCHK(c, hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (herr & 2) return fail(c, LCEMD_E_BAD_CSR, "query: column ids must be strictly increasing in [0, %lld)", (long long)c->v);
+    if (herr & 4) return fail(c, LCEMD_E_BAD_CSR, "query: weights must be finite and > 0");
+    if (herr & 8) return fail(c, LCEMD_E_BAD_CSR, "query: a row does not sum to 1");
+    if (herr) return fail(c, LCEMD_E_BAD_CSR, "query: malformed CSR");
+    Q.ptr = q->rowptr;
+    Q.col = q->col;
+    Q.val = q->val;
+  }
+  return LCEMD_OK;
+}
+
+int check_opts(lcemd_ctx* c, const lcemd_opts* o) {
+  if (!o) return fail(c, LCEMD_E_INVALID_ARG, "opts must not be NULL");
+  if (o->method < LCEMD_RWMD || o->method > LCEMD_ICT) return fail(c, LCEMD_E_INVALID_ARG, "unknown method %d", o->method);
+  if (o->method == LCEMD_ACT && (o->k < 1 || o->k > LCEMD_MAX_K))
+    return fail(c, LCEMD_E_INVALID_ARG, "ACT needs 1 <= k <= %d (got %d)", LCEMD_MAX_K, o->k);
+  if (o->direction < LCEMD_D2Q || o->direction > LCEMD_SYM) return fail(c, LCEMD_E_INVALID_ARG, "unknown direction %d", o->direction);
+  if (o->precision < LCEMD_FP32 || o->precision > LCEMD_FP8) return fail(c, LCEMD_E_INVALID_ARG, "unknown precision %d", o->precision);
+  if (o->precision != LCEMD_FP32) return fail(c, LCEMD_E_UNSUPPORTED, "only LCEMD_FP32 phase 1 is built");
+  for (int i = 0; i < 3; ++i)
+    if (o->reserved[i]) return fail(c, LCEMD_E_INVALID_ARG, "reserved option fields must be 0");
+  return LCEMD_OK;
+}
+
+int check_ready(lcemd_ctx* c) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  if (!c->V) return fail(c, LCEMD_E_NOT_LOADED, "embeddings not loaded");
+  if (!c->xptr) return fail(c, LCEMD_E_NOT_LOADED, "database not loaded");
+  return LCEMD_OK;
+}
+
+// table depth (entries per table row) for a method
+int table_depth(const lcemd_opts* o, int hmax) {
+  switch (o->method) {
+    case LCEMD_RWMD: return 1;
+    case LCEMD_OMR: return std::min(2, hmax);
+    case LCEMD_ACT: return std::min(o->k, hmax);
+    default: return std::min(64, hmax);  // ICT: first try; widened on overflow
+  }
+}
+
+P1Args base_args(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o) {
+  P1Args a;
+  memset(&a, 0, sizeof a);
+  a.V = c->V;
+  a.vnorm = c->vnorm;
+  a.Vb = c->Vb;
+  a.m_pad = c->m_pad;
+  a.method = o->method;
+  a.k = o->method == LCEMD_ACT ? o->k : 1;
+  a.n = c->n;
+  a.xptr = c->xptr;
+  a.xcv = c->xcv;
+  a.xcol = c->xcol;
+  a.v_used = c->v_used;
+  a.used = c->used;
+  a.xmax = c->xmax;
+  a.qptr = Q.ptr;
+  a.qcol = Q.col;
+  a.qval = Q.val;
+  return a;
+}
+
+// D2Q distances of every query against every database row (Sec. 4):
+// out[b * ld + u].
+int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
+  int KT = table_depth(o, Q.hmax);
+  const size_t per_q = (size_t)c->v_used * sizeof(float2);
+  int* ovf;
+  int rc;
+  if ((rc = wsget(c, "ovf", 1, ovf))) return rc;
+  int64_t q0 = 0;
+  while (q0 < Q.B) {
+    int64_t Bt = (int64_t)std::max<size_t>(1, c->table_budget / (per_q * KT));
+    Bt = std::min<int64_t>(Bt, 65535);
+    const int64_t nq = std::min<int64_t>(Bt, Q.B - q0);
+    float2* ZW;
+    if ((rc = wsget(c, "zw", (size_t)nq * c->v_used * KT, ZW))) return rc;
+    HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
+    P1Args a = base_args(c, Q, o);
+    a.KT = KT;
+    a.q0 = q0;
+    a.nq = nq;
+    a.ZW = ZW;
+    a.overflow = ovf;
+    int64_t H = Q.hptr[q0 + nq] - Q.hptr[q0];
+    if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)c->v_used * (double)H * (double)c->m))) return rc;
+    HIPCHK(c, launch_phase1(a, P1_TABLE, Q.hmax, PREC_F32, c->stream));
+    if ((rc = prof_end(c))) return rc;
+    if (o->method == LCEMD_ICT && KT < Q.hmax) {
+      int h_ovf = 0;
+      HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (h_ovf) {  // some row needs a deeper table: widen and redo this tile
+        KT = Q.hmax;
+        continue;
+      }
+    }
+    const double a2 = (double)nq * (8.0 * c->nnz + 8.0 * (c->n + 1) + 8.0 * (double)c->v_used * KT + 4.0 * c->n);
+    if ((rc = prof_begin(c, "phase2", a2))) return rc;
+    HIPCHK(c, launch_phase2(c->xptr, c->xcv, c->n, ZW, c->v_used, KT, nq, out + q0 * ld, ld, c->stream));
+    if ((rc = prof_end(c))) return rc;
+    q0 += nq;
+  }
+  return LCEMD_OK;
+}
+
+// Q2D for an explicit list of pairs or candidates (see P1Args).
+int run_pairs(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, P1Args a, float* out,
+              int64_t out_ld, int64_t per_row) {
+  const int rb_max = (Q.hmax + kRows - 1) / kRows;
+  float* partial;
+  int rc;
+  if ((rc = wsget(c, "partial", (size_t)a.npairs * rb_max, partial))) return rc;
+  a.rb_max = rb_max;
+  a.partial = partial;
+  if ((rc = prof_begin(c, "phase1_pair_q2d", (double)a.npairs))) return rc;
+  HIPCHK(c, launch_phase1(a, P1_PAIR, c->db_hmax, PREC_F32, c->stream));
+  if ((rc = prof_end(c))) return rc;
+  HIPCHK(c, launch_pair_reduce(partial, a.npairs, rb_max, out, out_ld, per_row, c->stream));
+  (void)o;
+  return LCEMD_OK;
+}
+
+// Full Q2D matrix: out[b * ld + u], in query tiles that keep the pair grid
+// within limits.
+int run_q2d_full(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
+  const int64_t per_launch = std::max<int64_t>(1, (int64_t(1) << 26) / c->n);
+  for (int64_t q0 = 0; q0 < Q.B; q0 += per_launch) {
+    const int64_t nq = std::min(per_launch, Q.B - q0);
+    P1Args a = base_args(c, Q, o);
+    a.q0 = q0;
+    a.npairs = nq * c->n;
+    int rc = run_pairs(c, Q, o, a, out + q0 * ld, ld, c->n);
+    if (rc) return rc;
+  }
+  return LCEMD_OK;
+}
+
+int finish_call(lcemd_ctx* c) {
+  int rc = prof_collect(c);
+  if (rc) return rc;
+  HIPCHK(c, hipGetLastError());
+  return LCEMD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int lcemd_version(void) { return LCEMD_VERSION; }
+
+int lcemd_create(lcemd_ctx** out, int device) {
+  if (!out) return LCEMD_E_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    g_create_error = "no HIP device available";
+    return LCEMD_E_NO_DEVICE;
+  }
+  if (device < 0 || device >= count) {
+    g_create_error = "device index out of range";
+    return LCEMD_E_NO_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    g_create_error = "hipGetDeviceProperties failed";
+    return LCEMD_E_NO_DEVICE;
+  }
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_create_error = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
+    return LCEMD_E_NO_DEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    g_create_error = "hipSetDevice failed";
+    return LCEMD_E_NO_DEVICE;
+  }
+  lcemd_ctx* c = new lcemd_ctx();
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    g_create_error = "hipStreamCreate failed";
+    return LCEMD_E_HIP;
+  }
+  c->stream = c->own_stream;
+  *out = c;
+  return LCEMD_OK;
+}
+
+void lcemd_destroy(lcemd_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  prof_reset(c);
+  free_db(c);
+  free_emb(c);
+  for (auto& kv : c->ws) dfree(kv.second.p);
+  c->ws.clear();
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+int lcemd_set_stream(lcemd_ctx* c, void* s) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  c->stream = s ? (hipStream_t)s : c->own_stream;
+  return LCEMD_OK;
+}
+
+const char* lcemd_last_error(const lcemd_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+int lcemd_load_embeddings(lcemd_ctx* c, const float* V, int64_t v, int32_t m, uint32_t flags) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  c->err.clear();
+  if (!V) return fail(c, LCEMD_E_INVALID_ARG, "V must not be NULL");
+  if (v < 1 || v >= (int64_t(1) << 31)) return fail(c, LCEMD_E_INVALID_ARG, "v out of range");
+  if (m < 1 || m > 4096) return fail(c, LCEMD_E_INVALID_ARG, "m out of range (1..4096)");
+  (void)hipSetDevice(c->device);
+  const bool dev = flags & LCEMD_PTR_DEVICE;
+  if (!dev) {
+    for (int64_t i = 0; i < v * (int64_t)m; ++i)
+      if (!std::isfinite(V[i])) return fail(c, LCEMD_E_INVALID_ARG, "embeddings must be finite");
+  }
+  free_db(c);
+  free_emb(c);
+  const int m_pad = ((m + kKChunk - 1) / kKChunk) * kKChunk;
+  int rc;
+  if ((rc = dalloc(c, c->V, (size_t)v * m_pad, "embeddings"))) return rc;
+  if ((rc = dalloc(c, c->vnorm, (size_t)v, "row norms"))) return rc;
+  const float* src = V;
+  float* tmp = nullptr;
+  if (!dev) {
+    if ((rc = dalloc(c, tmp, (size_t)v * m, "embedding staging"))) return rc;
+    HIPCHK(c, hipMemcpyAsync(tmp, V, sizeof(float) * v * m, hipMemcpyHostToDevice, c->stream));
+    src = tmp;
+  }
+  HIPCHK(c, launch_prep_embeddings(src, v, m, m_pad, (flags & LCEMD_L2_NORMALIZE) ? 1 : 0, c->V,
+                                   c->vnorm, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (tmp) (void)hipFree(tmp);
+  c->v = v;
+  c->m = m;
+  c->m_pad = m_pad;
+  return LCEMD_OK;
+}
+
+int lcemd_load_database(lcemd_ctx* c, const int64_t* rowptr, const int32_t* col, const float* val,
+                        int64_t n, uint32_t flags) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  c->err.clear();
+  if (!c->V) return fail(c, LCEMD_E_NOT_LOADED, "load embeddings before the database");
+  if (!rowptr || !col || !val) return fail(c, LCEMD_E_INVALID_ARG, "database arrays must not be NULL");
+  if (n < 1 || n >= (int64_t(1) << 31)) return fail(c, LCEMD_E_INVALID_ARG, "n out of range");
+  (void)hipSetDevice(c->device);
+  const bool dev = flags & LCEMD_PTR_DEVICE;
+  // host copies (the database is reorganised once, on the host)
+  std::vector<int64_t> hp;
+  std::vector<int32_t> hc;
+  std::vector<float> hv;
+  const int64_t* P = rowptr;
+  const int32_t* Cc = col;
+  const float* Vv = val;
+  if (dev) {
+    hp.resize(n + 1);
+    HIPCHK(c, hipMemcpy(hp.data(), rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+    int hm;
+    int rc = check_ptr_host(c, "database", hp.data(), n, &hm);
+    if (rc) return rc;
+    hc.resize(hp[n]);
+    hv.resize(hp[n]);
+    HIPCHK(c, hipMemcpy(hc.data(), col, sizeof(int32_t) * hp[n], hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(hv.data(), val, sizeof(float) * hp[n], hipMemcpyDeviceToHost));
+    P = hp.data();
+    Cc = hc.data();
+    Vv = hv.data();
+  }
+  const bool norm = flags & LCEMD_NORMALIZE;
+  int hmax = 0;
+  int rc = check_csr_host(c, "database", P, Cc, Vv, n, c->v, !norm, &hmax);
+  if (rc) return rc;
+  const int64_t nnz = P[n];
+  // weights (optionally renormalised with float64 row sums)
+  std::vector<float> w(Vv, Vv + nnz);
+  if (norm) {
+    for (int64_t r = 0; r < n; ++r) {
+      double s = 0.0;
+      for (int64_t i = P[r]; i < P[r + 1]; ++i) s += (double)w[i];
+      for (int64_t i = P[r]; i < P[r + 1]; ++i) w[i] = (float)((double)w[i] / s);
+    }
+  }
+  // used vocabulary (Sec. 2.2: union of the database's coordinates) and the
+  // largest weight each used word carries anywhere in the database
+  std::vector<int32_t> pos(c->v, -1);
+  std::vector<char> seen(c->v, 0);
+  for (int64_t i = 0; i < nnz; ++i) seen[Cc[i]] = 1;
+  std::vector<int32_t> used;
+  for (int64_t i = 0; i < c->v; ++i)
+    if (seen[i]) {
+      pos[i] = (int32_t)used.size();
+      used.push_back((int32_t)i);
+    }
+  std::vector<float> xmax(used.size(), 0.f);
+  std::vector<int2> cv(nnz);
+  for (int64_t i = 0; i < nnz; ++i) {
+    const int32_t p = pos[Cc[i]];
+    cv[i].x = p;
+    float wi = w[i];
+    memcpy(&cv[i].y, &wi, sizeof(float));
+    xmax[p] = std::max(xmax[p], wi);
+  }
+  free_db(c);
+  if ((rc = dalloc(c, c->xptr, n + 1, "rowptr")) || (rc = dalloc(c, c->xcv, nnz, "database entries")) ||
+      (rc = dalloc(c, c->xcol, nnz, "database word ids")) || (rc = dalloc(c, c->used, used.size(), "used vocabulary")) ||
+      (rc = dalloc(c, c->xmax, used.size(), "word maxima"))) {
+    free_db(c);
+    return rc;
+  }
+  HIPCHK(c, hipMemcpy(c->xptr, P, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->xcv, cv.data(), sizeof(int2) * nnz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->xcol, Cc, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->used, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->xmax, xmax.data(), sizeof(float) * used.size(), hipMemcpyHostToDevice));
+  c->n = n;
+  c->nnz = nnz;
+  c->v_used = (int64_t)used.size();
+  c->db_hmax = hmax;
+  c->used_host = std::move(used);
+  return LCEMD_OK;
+}
+
+int lcemd_check_histograms(const int64_t* rowptr, const int32_t* col, const float* val,
+                           int64_t rows, int64_t v, int require_normalized, char* msg,
+                           size_t msg_cap) {
+  lcemd_ctx scratch;  // only its error string is used
+  int rc;
+  int hmax = 0;
+  if (!rowptr || !col || !val) rc = fail(&scratch, LCEMD_E_INVALID_ARG, "arrays must not be NULL");
+  else if (rows < 1) rc = fail(&scratch, LCEMD_E_INVALID_ARG, "need at least one histogram");
+  else if (v < 1) rc = fail(&scratch, LCEMD_E_INVALID_ARG, "vocabulary must not be empty");
+  else rc = check_csr_host(&scratch, "histograms", rowptr, col, val, rows, v, require_normalized != 0, &hmax);
+  if (msg && msg_cap) snprintf(msg, msg_cap, "%s", scratch.err.c_str());
+  return rc;
+}
+
+int64_t lcemd_used_vocab(lcemd_ctx* c, int32_t* ids) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  if (ids && !c->used_host.empty()) memcpy(ids, c->used_host.data(), sizeof(int32_t) * c->used_host.size());
+  return (int64_t)c->used_host.size();
+}
+
+int lcemd_profile(lcemd_ctx* c, int enable) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  c->prof = enable != 0;
+  return LCEMD_OK;
+}
+
+int lcemd_profile_get(lcemd_ctx* c, lcemd_phase_time* out, int cap) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  const int cnt = (int)c->last.size();
+  for (int i = 0; i < cnt && i < cap && out; ++i) out[i] = c->last[i];
+  return cnt;
+}
+
+int lcemd_distances(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, float* out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  c->err.clear();
+  if ((rc = check_opts(c, o))) return rc;
+  if (!out) return fail(c, LCEMD_E_INVALID_ARG, "out must not be NULL");
+  (void)hipSetDevice(c->device);
+  prof_reset(c);
+  QDev Q;
+  if ((rc = stage_query(c, q, Q))) return rc;
+  const int64_t n = c->n;
+  float* dout = out;
+  if (!Q.device && (rc = wsget(c, "dist_out", (size_t)Q.B * n, dout))) return rc;
+  if (o->direction == LCEMD_D2Q || o->direction == LCEMD_SYM) {
+    if ((rc = run_d2q(c, Q, o, dout, n))) return rc;
+  }
+  if (o->direction == LCEMD_Q2D) {
+    if ((rc = run_q2d_full(c, Q, o, dout, n))) return rc;
+  } else if (o->direction == LCEMD_SYM) {
+    float* tmp;
+    if ((rc = wsget(c, "q2d_full", (size_t)Q.B * n, tmp))) return rc;
+    if ((rc = run_q2d_full(c, Q, o, tmp, n))) return rc;
+    HIPCHK(c, launch_max_inplace(dout, tmp, Q.B * n, c->stream));
+  }
+  if (!Q.device) {
+    HIPCHK(c, hipMemcpyAsync(out, dout, sizeof(float) * Q.B * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return finish_call(c);
+}
+
+int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t l, int64_t* idx,
+               float* dist) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  c->err.clear();
+  if ((rc = check_opts(c, o))) return rc;
+  if (!idx || !dist) return fail(c, LCEMD_E_INVALID_ARG, "idx/dist must not be NULL");
+  const int64_t n = c->n;
+  const int64_t avail = n - (o->exclude_self >= 0 ? 1 : 0);
+  if (l < 1 || l > LCEMD_MAX_L || l > avail)
+    return fail(c, LCEMD_E_INVALID_ARG, "need 1 <= l <= min(%d, %lld)", LCEMD_MAX_L, (long long)avail);
+  (void)hipSetDevice(c->device);
+  prof_reset(c);
+  QDev Q;
+  if ((rc = stage_query(c, q, Q))) return rc;
+  const int64_t B = Q.B;
+  if (o->exclude_self >= 0 && o->exclude_self + B > n)
+    return fail(c, LCEMD_E_INVALID_ARG, "exclude_self + B exceeds the database size");
+  int64_t* didx = idx;
+  float* ddist = dist;
+  if (!Q.device) {
+    if ((rc = wsget(c, "topl_idx", (size_t)B * l, didx)) || (rc = wsget(c, "topl_dist", (size_t)B * l, ddist))) return rc;
+  }
+  const int64_t excl = o->exclude_self >= 0 ? o->exclude_self : -1;
+  float* d2q;
+  if ((rc = wsget(c, "d2q_full", (size_t)B * n, d2q))) return rc;
+  if (o->direction == LCEMD_Q2D) {
+    if ((rc = run_q2d_full(c, Q, o, d2q, n))) return rc;
+  } else {
+    if ((rc = run_d2q(c, Q, o, d2q, n))) return rc;
+  }
+  if (o->direction != LCEMD_SYM) {
+    uint64_t* cand;
+    if ((rc = wsget(c, "cand", (size_t)B * l, cand))) return rc;
+    if ((rc = prof_begin(c, "select", (double)B * n))) return rc;
+    HIPCHK(c, launch_select(d2q, n, n, B, l, nullptr, excl, cand, c->stream));
+    if ((rc = prof_end(c))) return rc;
+    HIPCHK(c, launch_unpack_topl(cand, l, B, nullptr, l, didx, ddist, c->stream));
+  } else {
+    // exact symmetric top-l by lower-bound pruning (SYM >= D2Q)
+    std::vector<int32_t> rows(B);
+    for (int64_t b = 0; b < B; ++b) rows[b] = (int32_t)b;
+    int64_t Lp = std::max<int64_t>(4 * (int64_t)l, 64);
+    int32_t* drows;
+    int* dflags;
+    if ((rc = wsget(c, "sym_rows", (size_t)B, drows)) || (rc = wsget(c, "sym_flags", (size_t)B, dflags))) return rc;
+    std::vector<int> hflags;
+    while (!rows.empty()) {
+      const int64_t R = (int64_t)rows.size();
+      const int64_t use = std::min<int64_t>(Lp, avail);
+      const bool exhaustive = use >= avail;
+      const int64_t cld = exhaustive ? use : use + 1;
+      if (cld > kSelectBuf / 2) {
+        // too many candidates for the selection buffer: evaluate Q2D for
+        // every row of the remaining queries
+        float* q2 = nullptr;
+        if ((rc = wsget(c, "q2d_full", (size_t)B * n, q2))) return rc;
+        for (int64_t i = 0; i < R; ++i) {
+          P1Args a = base_args(c, Q, o);
+          a.q0 = rows[i];
+          a.npairs = n;
+          if ((rc = run_pairs(c, Q, o, a, q2 + (int64_t)rows[i] * n, n, n))) return rc;
+          HIPCHK(c, launch_max_inplace(d2q + (int64_t)rows[i] * n, q2 + (int64_t)rows[i] * n, n, c->stream));
+        }
+        HIPCHK(c, hipMemcpyAsync(drows, rows.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream));
+        uint64_t* cand;
+        if ((rc = wsget(c, "cand", (size_t)R * l, cand))) return rc;
+        HIPCHK(c, launch_select(d2q, n, n, R, l, drows, excl, cand, c->stream));
+        HIPCHK(c, launch_unpack_topl(cand, l, R, drows, l, didx, ddist, c->stream));
+        break;
+      }
+      HIPCHK(c, hipMemcpyAsync(drows, rows.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream));
+      uint64_t* cand;
+      float* q2v;
+      if ((rc = wsget(c, "cand", (size_t)R * cld, cand)) || (rc = wsget(c, "cand_q2d", (size_t)R * use, q2v))) return rc;
+      if ((rc = prof_begin(c, "select", (double)R * n))) return rc;
+      HIPCHK(c, launch_select(d2q, n, n, R, (int)cld, drows, excl, cand, c->stream));
+      if ((rc = prof_end(c))) return rc;
+      P1Args a = base_args(c, Q, o);
+      a.cand = cand;
+      a.cand_ld = cld;
+      a.cand_use = use;
+      a.qlist = drows;
+      a.npairs = R * use;
+      if ((rc = run_pairs(c, Q, o, a, q2v, use, use))) return rc;
+      HIPCHK(c, launch_finalize_sym(cand, cld, use, q2v, R, drows, n, l, didx, ddist, dflags, c->stream));
+      hflags.resize(R);
+      HIPCHK(c, hipMemcpyAsync(hflags.data(), dflags, sizeof(int) * R, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      std::vector<int32_t> again;
+      for (int64_t i = 0; i < R; ++i)
+        if (hflags[i]) again.push_back(rows[i]);
+      rows.swap(again);
+      Lp *= 4;
+    }
+  }
+  if (!Q.device) {
+    HIPCHK(c, hipMemcpyAsync(idx, didx, sizeof(int64_t) * B * l, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dist, ddist, sizeof(float) * B * l, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return finish_call(c);
+}
+
+int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t* S, float* Z,
+                 float* W) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  c->err.clear();
+  if (!o) return fail(c, LCEMD_E_INVALID_ARG, "opts must not be NULL");
+  if (o->k < 1 || o->k > LCEMD_MAX_K) return fail(c, LCEMD_E_INVALID_ARG, "need 1 <= k <= %d", LCEMD_MAX_K);
+  if (o->precision != LCEMD_FP32) return fail(c, LCEMD_E_UNSUPPORTED, "only LCEMD_FP32 phase 1 is built");
+  if (!S || !Z || !W) return fail(c, LCEMD_E_INVALID_ARG, "S/Z/W must not be NULL");
+  (void)hipSetDevice(c->device);
+  prof_reset(c);
+  QDev Q;
+  if ((rc = stage_query(c, q, Q))) return rc;
+  const size_t total = (size_t)Q.B * c->v_used * o->k;
+  int32_t* dS = S;
+  float *dZ = Z, *dW = W;
+  if (!Q.device) {
+    if ((rc = wsget(c, "tab_S", total, dS)) || (rc = wsget(c, "tab_Z", total, dZ)) || (rc = wsget(c, "tab_W", total, dW))) return rc;
+  }
+  lcemd_opts oo = *o;
+  oo.method = LCEMD_ACT;
+  P1Args a = base_args(c, Q, &oo);
+  a.k = o->k;
+  a.q0 = 0;
+  a.nq = Q.B;
+  a.S = dS;
+  a.Z = dZ;
+  a.W = dW;
+  if (Q.B > 65535) return fail(c, LCEMD_E_CAPACITY, "tables: at most 65535 queries per call");
+  HIPCHK(c, launch_phase1(a, P1_TABLE_FULL, Q.hmax, PREC_F32, c->stream));
+  if (!Q.device) {
+    HIPCHK(c, hipMemcpyAsync(S, dS, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(Z, dZ, sizeof(float) * total, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(W, dW, sizeof(float) * total, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return finish_call(c);
+}
+
+// serving entry points: implemented in server.cpp
+}  // extern "C"

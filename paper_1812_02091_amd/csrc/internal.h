@@ -1,0 +1,106 @@
+// Internal declarations of the lcemd library (host side + kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lcemd.h"
+
+namespace lcemd {
+
+// ---------------------------------------------------------------------------
+// constants shared by kernels and host planning
+// ---------------------------------------------------------------------------
+constexpr int kRows = 64;        // phase-1 rows per workgroup
+constexpr int kKChunk = 32;      // phase-1 K (embedding dim) chunk staged in LDS
+constexpr int kColChunk = 64;    // phase-1 columns per MFMA pass
+constexpr int kThreads = 256;    // threads per workgroup for every kernel
+constexpr int kSelectBuf = 2048; // LDS slots of the selection sort
+
+// How a phase-1 workgroup finds its rows and its column segment, and what
+// it emits.
+enum P1Mode : int {
+  P1_TABLE = 0,       // rows = used vocabulary block, segment = one query;
+                      // emits depth-limited (z, w) rows for phase 2
+  P1_TABLE_FULL = 1,  // same rows/segment; emits S, Z, W at full depth k_eff
+  P1_PAIR = 2,        // rows = one query's words, segment = one database row;
+                      // emits the summed per-row transfer cost (Q2D)
+};
+
+enum P1Prec : int { PREC_F32 = 0, PREC_BF16 = 1, PREC_FP8 = 2 };
+
+struct P1Args {
+  // embeddings
+  const float* V;         // [v][m_pad] float32, zero padded
+  const float* vnorm;     // [v] |v|^2 (float64 accumulation, stored float32)
+  const uint16_t* Vb;     // [v][m_pad] bfloat16 copy (PREC_BF16)
+  const uint8_t* V8;      // [v][m_pad] fp8 e4m3 copy (PREC_FP8)
+  const float* vscale;    // [v] fp8 row scales
+  int m_pad;
+  // measure
+  int method;             // LCEMD_RWMD / OMR / ACT / ICT
+  int k;                  // ACT k
+  int KT;                 // table stride (entries per table row)
+  // database
+  int64_t n;
+  const int64_t* xptr;    // [n+1]
+  const int2* xcv;        // [nnz] (compact word id, weight bits)
+  const int32_t* xcol;    // [nnz] original word ids
+  int64_t v_used;
+  const int32_t* used;    // [v_used] original id of each used word
+  const float* xmax;      // [v_used] largest database weight per used word
+  // queries
+  const int64_t* qptr;    // [B+1]
+  const int32_t* qcol;
+  const float* qval;
+  int64_t q0;             // first query of this launch (table modes)
+  int64_t nq;             // queries in this launch (table modes)
+  // pair mode
+  int64_t npairs;
+  const int64_t* pair_q;  // [npairs] query index, or NULL: full grid
+  const int64_t* pair_u;  // [npairs] database row, or NULL: full grid
+  const uint64_t* cand;   // candidate list (packed key | index), or NULL
+  int64_t cand_ld;        // candidates per query in `cand`
+  int64_t cand_use;       // candidates evaluated per query
+  const int32_t* qlist;   // query ids for candidate mode (NULL: identity)
+  int rb_max;             // row blocks per pair (grid y)
+  // outputs
+  float2* ZW;             // P1_TABLE: [nq][v_used][KT]
+  int32_t* S;             // P1_TABLE_FULL: [nq][v_used][k]
+  float* Z;
+  float* W;
+  float* partial;         // P1_PAIR: [npairs][rb_max]
+  int* overflow;          // set to 1 when a row needed more than KT entries
+};
+
+// kernel launchers (each in the translation unit of its kernel)
+hipError_t launch_phase1(const P1Args& a, int mode, int hmax, int prec, hipStream_t s);
+hipError_t launch_pair_reduce(const float* partial, int64_t npairs, int rb_max, float* out,
+                              int64_t out_ld, int64_t per_row, hipStream_t s);
+hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const float2* ZW,
+                         int64_t v_used, int KT, int64_t nq, float* out, int64_t ld,
+                         hipStream_t s);
+hipError_t launch_prep_embeddings(const float* Vin, int64_t v, int m, int m_pad, int l2norm,
+                                  float* Vpad, float* vnorm, hipStream_t s);
+hipError_t launch_make_bf16(const float* V, int64_t count, uint16_t* out, hipStream_t s);
+hipError_t launch_make_fp8(const float* V, int64_t v, int m_pad, uint8_t* out, float* scale,
+                           hipStream_t s);
+hipError_t launch_validate_csr(const int64_t* ptr, const int32_t* col, const float* val,
+                               int64_t rows, int64_t v, int normalized, int* err,
+                               hipStream_t s);
+hipError_t launch_select(const float* keys, int64_t ld, int64_t n, int64_t rows, int L,
+                         const int32_t* row_list, int64_t exclude_base, uint64_t* out,
+                         hipStream_t s);
+hipError_t launch_finalize_sym(const uint64_t* cand, int64_t cand_ld, int64_t cand_use,
+                               const float* q2d, int64_t rows, const int32_t* row_list,
+                               int64_t n, int L, int64_t* idx, float* dist, int* flags,
+                               hipStream_t s);
+hipError_t launch_unpack_topl(const uint64_t* cand, int64_t cand_ld, int64_t rows,
+                              const int32_t* row_list, int L, int64_t* idx, float* dist,
+                              hipStream_t s);
+hipError_t launch_max_inplace(float* a, const float* b, int64_t count, hipStream_t s);
+
+}  // namespace lcemd

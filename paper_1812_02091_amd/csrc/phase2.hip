@@ -1,0 +1,97 @@
+// Phase 2/3 of LC-ACT (Sec. 4, Eq. 6-9): for every non-zero X_ui of the
+// database, the capacity-limited transfers of its mass against the query's
+// table row for word i, summed per database row (document).
+//
+// Each table row holds (z, w) pairs in ascending distance order; its last
+// valid entry carries w = +inf, so the loop below is Eq. (6)-(8) followed by
+// Eq. (9) (the rest of the mass at the last distance) and always ends.
+//
+// Layout and mapping: a wave owns one database row at a time; its lanes
+// stride over the row's non-zeros (coalesced 8-byte (word, weight) loads),
+// apply QB queries' tables to each non-zero, then reduce across the wave
+// with a fixed butterfly.  The per-row sum therefore has a fixed order that
+// does not depend on which other queries or rows share the launch.
+#include "internal.h"
+
+namespace lcemd {
+
+constexpr int kDocsPerWave = 4;
+constexpr int kDocsPerWG = kDocsPerWave * (kThreads / 64);
+constexpr int kQB = 4;
+
+__device__ __forceinline__ float wave_sum(float t) {
+  t += __shfl_xor(t, 32);
+  t += __shfl_xor(t, 16);
+  t += __shfl_xor(t, 8);
+  t += __shfl_xor(t, 4);
+  t += __shfl_xor(t, 2);
+  t += __shfl_xor(t, 1);
+  return t;
+}
+
+__global__ __launch_bounds__(kThreads) void k_phase2(const int64_t* __restrict__ xptr,
+                                                     const int2* __restrict__ xcv, int64_t n,
+                                                     const float2* __restrict__ ZW, int64_t v_used,
+                                                     int KT, int64_t nq, float* __restrict__ out,
+                                                     int64_t ld) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q0 = (int64_t)blockIdx.y * kQB;
+  const int nqb = (int)min((int64_t)kQB, nq - q0);
+  const int64_t ubase = (int64_t)blockIdx.x * kDocsPerWG + wave * kDocsPerWave;
+  for (int j = 0; j < kDocsPerWave; ++j) {
+    const int64_t u = ubase + j;
+    if (u >= n) break;
+    const int64_t e0 = xptr[u], e1 = xptr[u + 1];
+    float t[kQB];
+#pragma unroll
+    for (int q = 0; q < kQB; ++q) t[q] = 0.f;
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
+      const int2 cv = xcv[e];
+      const float x = __int_as_float(cv.y);
+#pragma unroll
+      for (int q = 0; q < kQB; ++q) {
+        if (q < nqb) {
+          const float2* row = ZW + ((q0 + q) * v_used + cv.x) * (int64_t)KT;
+          float rem = x, acc = 0.f;
+          for (int l = 0; l < KT; ++l) {
+            const float2 zw = row[l];
+            const float r = fminf(rem, zw.y);
+            rem -= r;
+            acc = fmaf(r, zw.x, acc);
+            if (rem <= 0.f) break;
+          }
+          t[q] += acc;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kQB; ++q) {
+      const float s = wave_sum(t[q]);
+      if (lane == 0 && q < nqb) out[(q0 + q) * ld + u] = s;
+    }
+  }
+}
+
+hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const float2* ZW,
+                         int64_t v_used, int KT, int64_t nq, float* out, int64_t ld,
+                         hipStream_t s) {
+  if (n <= 0 || nq <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n + kDocsPerWG - 1) / kDocsPerWG), (unsigned)((nq + kQB - 1) / kQB));
+  hipLaunchKernelGGL(k_phase2, grid, dim3(kThreads), 0, s, xptr, xcv, n, ZW, v_used, KT, nq, out,
+                     ld);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void k_max_inplace(float* a, const float* b, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < count) a[i] = fmaxf(a[i], b[i]);
+}
+
+hipError_t launch_max_inplace(float* a, const float* b, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_max_inplace, dim3((unsigned)((count + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, a, b, count);
+  return hipGetLastError();
+}
+
+}  // namespace lcemd

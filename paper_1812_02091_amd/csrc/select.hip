@@ -1,0 +1,160 @@
+// Top-l selection (Sec. 5: the l nearest database histograms per query) and
+// the exact symmetric search.
+//
+// Keys are packed as (order-preserving bits of the float32 distance) << 32
+// | database row index, so one unsigned comparison orders by (distance,
+// index) and ties go to the lower index.  Selection keeps a running best
+// list at the front of an LDS buffer, refills the rest with the next chunk
+// of a query's distances and bitonic-sorts the buffer.
+//
+// Symmetric top-l (Sec. 2.1/5: SYM = max(D2Q, Q2D) >= D2Q): the first L
+// candidates by D2Q get their Q2D evaluated; the l best by SYM among them
+// are exact as soon as the (L+1)-th candidate's D2Q key exceeds the l-th
+// best SYM key, since every other row's SYM key is at least its D2Q key.
+// Rows for which that certificate fails are flagged for a wider pass.
+#include "internal.h"
+
+namespace lcemd {
+
+__device__ __forceinline__ uint32_t order_bits_s(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ uint64_t pack_s(float f, uint32_t idx) {
+  return ((uint64_t)order_bits_s(f) << 32) | (uint64_t)idx;
+}
+__device__ __forceinline__ float unpack_f(uint64_t k) {
+  const uint32_t o = (uint32_t)(k >> 32);
+  const uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  return __uint_as_float(u);
+}
+
+// Ascending bitonic sort of N (power of two) keys in LDS by all threads.
+template <int N>
+__device__ void bitonic_sort(uint64_t* buf) {
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N / 2; i += kThreads) {
+        const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+        const int hi = lo + j;
+        const bool asc = (lo & k) == 0;
+        const uint64_t x = buf[lo], y = buf[hi];
+        if ((x > y) == asc) {
+          buf[lo] = y;
+          buf[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_select(const float* __restrict__ keys, int64_t ld,
+                                                     int64_t n, int L,
+                                                     const int32_t* __restrict__ row_list,
+                                                     int64_t exclude_base,
+                                                     uint64_t* __restrict__ out) {
+  __shared__ uint64_t buf[kSelectBuf];
+  const int64_t ri = blockIdx.x;
+  const int64_t b = row_list ? (int64_t)row_list[ri] : ri;
+  const float* kr = keys + b * ld;
+  const int64_t excl = exclude_base >= 0 ? exclude_base + b : -1;
+  for (int i = threadIdx.x; i < kSelectBuf; i += kThreads) buf[i] = ~0ull;
+  const int fill = kSelectBuf - L;
+  for (int64_t s0 = 0; s0 < n; s0 += fill) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < fill; i += kThreads) {
+      const int64_t u = s0 + i;
+      uint64_t kk = ~0ull;
+      if (u < n && u != excl) kk = pack_s(kr[u], (uint32_t)u);
+      buf[L + i] = kk;
+    }
+    __syncthreads();
+    bitonic_sort<kSelectBuf>(buf);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < L; i += kThreads) out[ri * L + i] = buf[i];
+}
+
+hipError_t launch_select(const float* keys, int64_t ld, int64_t n, int64_t rows, int L,
+                         const int32_t* row_list, int64_t exclude_base, uint64_t* out,
+                         hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (L < 1 || L > kSelectBuf / 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_select, dim3((unsigned)rows), dim3(kThreads), 0, s, keys, ld, n, L,
+                     row_list, exclude_base, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void k_finalize_sym(
+    const uint64_t* __restrict__ cand, int64_t cand_ld, int64_t cand_use,
+    const float* __restrict__ q2d, const int32_t* __restrict__ row_list, int64_t n, int L,
+    int64_t* __restrict__ idx, float* __restrict__ dist, int* __restrict__ flags) {
+  __shared__ uint64_t buf[kSelectBuf];
+  const int64_t ri = blockIdx.x;
+  const int64_t b = row_list ? (int64_t)row_list[ri] : ri;
+  const uint64_t* cr = cand + ri * cand_ld;
+  for (int i = threadIdx.x; i < kSelectBuf; i += kThreads) {
+    uint64_t kk = ~0ull;
+    if (i < cand_use) {
+      const uint64_t c = cr[i];
+      if (c != ~0ull) {
+        const float s = fmaxf(unpack_f(c), q2d[ri * cand_use + i]);
+        kk = pack_s(s, (uint32_t)c);
+      }
+    }
+    buf[i] = kk;
+  }
+  __syncthreads();
+  bitonic_sort<kSelectBuf>(buf);
+  for (int i = threadIdx.x; i < L; i += kThreads) {
+    const uint64_t kk = buf[i];
+    idx[b * L + i] = kk == ~0ull ? -1 : (int64_t)(uint32_t)kk;
+    dist[b * L + i] = kk == ~0ull ? INFINITY : unpack_f(kk);
+  }
+  if (threadIdx.x == 0) {
+    int f = 0;
+    if (cand_use < cand_ld) {
+      const uint64_t next = cr[cand_use];
+      if (next != ~0ull && next <= buf[L - 1]) f = 1;
+    }
+    flags[ri] = f;
+  }
+}
+
+hipError_t launch_finalize_sym(const uint64_t* cand, int64_t cand_ld, int64_t cand_use,
+                               const float* q2d, int64_t rows, const int32_t* row_list,
+                               int64_t n, int L, int64_t* idx, float* dist, int* flags,
+                               hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (cand_use > kSelectBuf || L > cand_use) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finalize_sym, dim3((unsigned)rows), dim3(kThreads), 0, s, cand, cand_ld,
+                     cand_use, q2d, row_list, n, L, idx, dist, flags);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpack_topl(const uint64_t* __restrict__ cand,
+                                                          int64_t cand_ld, int64_t rows,
+                                                          const int32_t* __restrict__ row_list,
+                                                          int L, int64_t* __restrict__ idx,
+                                                          float* __restrict__ dist) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= rows * L) return;
+  const int64_t ri = t / L, i = t % L;
+  const int64_t b = row_list ? (int64_t)row_list[ri] : ri;
+  const uint64_t kk = cand[ri * cand_ld + i];
+  idx[b * L + i] = kk == ~0ull ? -1 : (int64_t)(uint32_t)kk;
+  dist[b * L + i] = kk == ~0ull ? INFINITY : unpack_f(kk);
+}
+
+hipError_t launch_unpack_topl(const uint64_t* cand, int64_t cand_ld, int64_t rows,
+                              const int32_t* row_list, int L, int64_t* idx, float* dist,
+                              hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const int64_t total = rows * L;
+  hipLaunchKernelGGL(k_unpack_topl, dim3((unsigned)((total + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, cand, cand_ld, rows, row_list, L, idx, dist);
+  return hipGetLastError();
+}
+
+}  // namespace lcemd

@@ -1,0 +1,320 @@
+"""Python binding of the lcemd C-ABI (include/lcemd.h): argument marshalling
+only.  Every step of the computation runs in the HIP library; there is no
+fallback.  numpy arrays go through the host-pointer path; torch tensors on
+the GPU go through the device-pointer path on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblcemd.so")
+
+OK = 0
+E_INVALID_ARG, E_BAD_CSR, E_NOT_LOADED, E_OOM, E_HIP, E_UNSUPPORTED, E_CAPACITY, E_NO_DEVICE = (
+    -1, -2, -3, -4, -5, -6, -7, -8)
+RWMD, OMR, ACT, ICT = 0, 1, 2, 3
+D2Q, Q2D, SYM = 0, 1, 2
+FP32, BF16, FP8 = 0, 1, 2
+PTR_DEVICE, NORMALIZE, L2_NORMALIZE = 0x1, 0x2, 0x4
+MAX_HIST, MAX_L, MAX_K = 512, 1024, 512
+
+METHOD = {"rwmd": RWMD, "omr": OMR, "act": ACT, "ict": ICT}
+DIRECTION = {"d2q": D2Q, "q2d": Q2D, "sym": SYM}
+PRECISION = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
+
+
+class LcemdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lcemd error {code}: {msg}")
+        self.code = code
+
+
+class lcemd_query(C.Structure):
+    _fields_ = [("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("B", C.c_int64), ("flags", C.c_uint32)]
+
+
+class lcemd_opts(C.Structure):
+    _fields_ = [("method", C.c_int32), ("k", C.c_int32), ("direction", C.c_int32),
+                ("precision", C.c_int32), ("exclude_self", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
+
+
+class lcemd_phase_time(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("ms", C.c_double), ("launches", C.c_int64),
+                ("work", C.c_double)]
+
+
+class lcemd_server_cfg(C.Structure):
+    _fields_ = [("method", C.c_int32), ("k", C.c_int32), ("precision", C.c_int32),
+                ("l", C.c_int32), ("max_slots", C.c_int32), ("max_batch_words", C.c_int32),
+                ("memory_budget", C.c_int64), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
+# every symbol the header declares, with its ctypes signature
+_SIGS = {
+    "lcemd_version": (C.c_int, []),
+    "lcemd_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    "lcemd_destroy": (None, [C.c_void_p]),
+    "lcemd_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lcemd_last_error": (C.c_char_p, [C.c_void_p]),
+    "lcemd_load_embeddings": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_uint32]),
+    "lcemd_load_database": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.c_uint32]),
+    "lcemd_distances": (C.c_int, [C.c_void_p, C.POINTER(lcemd_query), C.POINTER(lcemd_opts),
+                                  C.c_void_p]),
+    "lcemd_topl": (C.c_int, [C.c_void_p, C.POINTER(lcemd_query), C.POINTER(lcemd_opts), C.c_int32,
+                             C.c_void_p, C.c_void_p]),
+    "lcemd_tables": (C.c_int, [C.c_void_p, C.POINTER(lcemd_query), C.POINTER(lcemd_opts),
+                               C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lcemd_used_vocab": (C.c_int64, [C.c_void_p, C.c_void_p]),
+    "lcemd_profile": (C.c_int, [C.c_void_p, C.c_int]),
+    "lcemd_profile_get": (C.c_int, [C.c_void_p, C.POINTER(lcemd_phase_time), C.c_int]),
+    "lcemd_server_start": (C.c_int, [C.c_void_p, C.POINTER(lcemd_server_cfg),
+                                     C.POINTER(C.c_void_p)]),
+    "lcemd_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                      C.POINTER(C.c_uint64)]),
+    "lcemd_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                    C.POINTER(C.c_double)]),
+    "lcemd_server_stop": (None, [C.c_void_p]),
+    "lcemd_check_histograms": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                         C.c_int, C.c_char_p, C.c_size_t]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblcemd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1812_02091_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+class _Arg:
+    """One array argument: keeps the owning object alive, exposes its address."""
+
+    def __init__(self, x, dtype, device: bool):
+        if device:
+            import torch
+
+            tdt = {np.int64: torch.int64, np.int32: torch.int32, np.float32: torch.float32}[dtype]
+            if not (_is_torch(x) and x.is_cuda):
+                raise TypeError("device call: every array must be a GPU torch tensor")
+            if x.dtype != tdt:
+                raise TypeError(f"expected {tdt}, got {x.dtype}")
+            self.obj = x.contiguous()
+            self.ptr = self.obj.data_ptr()
+        else:
+            if _is_torch(x):
+                x = x.detach().cpu().numpy()
+            self.obj = np.ascontiguousarray(x, dtype=dtype)
+            self.ptr = self.obj.ctypes.data
+
+
+def _device_mode(*xs) -> bool:
+    d = [(_is_torch(x) and x.is_cuda) for x in xs]
+    if any(d) and not all(d):
+        raise TypeError("mix of host and GPU arrays")
+    return all(d)
+
+
+def _opts(method, k, direction, precision, exclude_self=-1):
+    o = lcemd_opts()
+    o.method = METHOD[method] if isinstance(method, str) else int(method)
+    o.k = int(k)
+    o.direction = DIRECTION[direction] if isinstance(direction, str) else int(direction)
+    o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.exclude_self = int(exclude_self)
+    return o
+
+
+class Context:
+    """One lcemd context on one GPU (the same names as the C entry points)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        h = C.c_void_p()
+        rc = self.lib.lcemd_create(C.byref(h), int(device))
+        if rc != OK:
+            raise LcemdError(rc, self.lib.lcemd_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lcemd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            raise LcemdError(rc, self.lib.lcemd_last_error(self.h).decode())
+        return rc
+
+    def last_error(self) -> str:
+        return self.lib.lcemd_last_error(self.h).decode()
+
+    def _sync_stream(self, device: bool):
+        if device:
+            import torch
+
+            self._check(self.lib.lcemd_set_stream(self.h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        else:
+            self._check(self.lib.lcemd_set_stream(self.h, None))
+
+    # ---- loads ----
+    def load_embeddings(self, V, l2_normalize: bool = False):
+        dev = _device_mode(V)
+        self._sync_stream(dev)
+        a = _Arg(V, np.float32, dev)
+        v, m = a.obj.shape
+        flags = (PTR_DEVICE if dev else 0) | (L2_NORMALIZE if l2_normalize else 0)
+        self._check(self.lib.lcemd_load_embeddings(self.h, C.c_void_p(a.ptr), v, m, flags))
+
+    def load_database(self, rowptr, col, val, normalize: bool = False):
+        dev = _device_mode(rowptr, col, val)
+        self._sync_stream(dev)
+        p, c, v = _Arg(rowptr, np.int64, dev), _Arg(col, np.int32, dev), _Arg(val, np.float32, dev)
+        n = p.obj.shape[0] - 1
+        flags = (PTR_DEVICE if dev else 0) | (NORMALIZE if normalize else 0)
+        self._check(self.lib.lcemd_load_database(self.h, C.c_void_p(p.ptr), C.c_void_p(c.ptr),
+                                                 C.c_void_p(v.ptr), n, flags))
+        self._n = int(n)
+
+    def used_vocab(self) -> np.ndarray:
+        cnt = self.lib.lcemd_used_vocab(self.h, None)
+        out = np.empty(max(cnt, 0), dtype=np.int32)
+        self.lib.lcemd_used_vocab(self.h, C.c_void_p(out.ctypes.data))
+        return out
+
+    # ---- queries ----
+    def _query(self, qptr, qcol, qval):
+        dev = _device_mode(qptr, qcol, qval)
+        self._sync_stream(dev)
+        p, c, v = _Arg(qptr, np.int64, dev), _Arg(qcol, np.int32, dev), _Arg(qval, np.float32, dev)
+        q = lcemd_query()
+        q.rowptr, q.col, q.val = p.ptr, c.ptr, v.ptr
+        q.B = p.obj.shape[0] - 1
+        q.flags = PTR_DEVICE if dev else 0
+        return q, (p, c, v), dev
+
+    def distances(self, qptr, qcol, qval, method="act", k=1, direction="sym", precision="fp32",
+                  n: Optional[int] = None, out=None):
+        """B x n distances; host numpy in -> numpy out, GPU tensors in ->
+        GPU tensor out (``out`` may be given)."""
+        q, keep, dev = self._query(qptr, qcol, qval)
+        o = _opts(method, k, direction, precision)
+        n = self.n if n is None else n
+        if dev:
+            import torch
+
+            if out is None:
+                out = torch.empty((q.B, n), dtype=torch.float32, device=qptr.device)
+            ptr = out.data_ptr()
+        else:
+            out = np.empty((q.B, n), dtype=np.float32)
+            ptr = out.ctypes.data
+        self._check(self.lib.lcemd_distances(self.h, C.byref(q), C.byref(o), C.c_void_p(ptr)))
+        return out
+
+    def topl(self, qptr, qcol, qval, l, method="act", k=1, direction="sym", precision="fp32",
+             exclude_self=-1, out=None):
+        q, keep, dev = self._query(qptr, qcol, qval)
+        o = _opts(method, k, direction, precision, exclude_self)
+        if dev:
+            import torch
+
+            if out is None:
+                out = (torch.empty((q.B, l), dtype=torch.int64, device=qptr.device),
+                       torch.empty((q.B, l), dtype=torch.float32, device=qptr.device))
+            pi, pd = out[0].data_ptr(), out[1].data_ptr()
+        else:
+            out = (np.empty((q.B, l), dtype=np.int64), np.empty((q.B, l), dtype=np.float32))
+            pi, pd = out[0].ctypes.data, out[1].ctypes.data
+        self._check(self.lib.lcemd_topl(self.h, C.byref(q), C.byref(o), int(l), C.c_void_p(pi),
+                                        C.c_void_p(pd)))
+        return out
+
+    def tables(self, qptr, qcol, qval, k, precision="fp32"):
+        q, keep, dev = self._query(qptr, qcol, qval)
+        o = _opts("act", k, "d2q", precision)
+        nu = self.lib.lcemd_used_vocab(self.h, None)
+        shape = (q.B, nu, k)
+        if dev:
+            import torch
+
+            S = torch.empty(shape, dtype=torch.int32, device=qptr.device)
+            Z = torch.empty(shape, dtype=torch.float32, device=qptr.device)
+            W = torch.empty(shape, dtype=torch.float32, device=qptr.device)
+            ptrs = (S.data_ptr(), Z.data_ptr(), W.data_ptr())
+        else:
+            S = np.empty(shape, dtype=np.int32)
+            Z = np.empty(shape, dtype=np.float32)
+            W = np.empty(shape, dtype=np.float32)
+            ptrs = (S.ctypes.data, Z.ctypes.data, W.ctypes.data)
+        self._check(self.lib.lcemd_tables(self.h, C.byref(q), C.byref(o), *[C.c_void_p(p) for p in ptrs]))
+        return S, Z, W
+
+    # ---- profiling ----
+    def profile(self, enable: bool = True):
+        self._check(self.lib.lcemd_profile(self.h, int(bool(enable))))
+
+    def profile_get(self):
+        cnt = self.lib.lcemd_profile_get(self.h, None, 0)
+        arr = (lcemd_phase_time * max(cnt, 1))()
+        self.lib.lcemd_profile_get(self.h, arr, cnt)
+        return [dict(name=arr[i].name.decode(), ms=arr[i].ms, launches=arr[i].launches,
+                     work=arr[i].work) for i in range(cnt)]
+
+    @property
+    def n(self) -> int:
+        return self._n
+
+    @n.setter
+    def n(self, value):
+        self._n = value
+
+
+def check_histograms(rowptr, col, val, v: int, require_normalized: bool = True):
+    """Host-side validation of a CSR histogram batch (no GPU needed): returns
+    (status code, message)."""
+    lib = load_library()
+    p, c, w = _Arg(rowptr, np.int64, False), _Arg(col, np.int32, False), _Arg(val, np.float32, False)
+    msg = C.create_string_buffer(512)
+    rc = lib.lcemd_check_histograms(C.c_void_p(p.ptr), C.c_void_p(c.ptr), C.c_void_p(w.ptr),
+                                    p.obj.shape[0] - 1, int(v), int(require_normalized), msg, 512)
+    return rc, msg.value.decode()
+
+
+def open_context(V, db_rowptr, db_col, db_val, device: int = 0, l2_normalize: bool = False) -> Context:
+    """Context with embeddings and database loaded."""
+    ctx = Context(device)
+    ctx.load_embeddings(V, l2_normalize=l2_normalize)
+    ctx.load_database(db_rowptr, db_col, db_val)
+    ctx.n = int(db_rowptr.shape[0] - 1)
+    return ctx

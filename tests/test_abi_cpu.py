@@ -1,0 +1,112 @@
+"""The C-ABI library without a GPU: it loads, exports every entry point
+include/lcemd.h declares, and its host-side validation rejects malformed
+histograms with the documented status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1812_02091_amd import lcemd as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lcemd.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lcemd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared_functions()
+    for must in ("lcemd_create", "lcemd_destroy", "lcemd_load_embeddings", "lcemd_load_database",
+                 "lcemd_distances", "lcemd_topl", "lcemd_tables", "lcemd_last_error",
+                 "lcemd_server_start", "lcemd_server_submit", "lcemd_server_wait",
+                 "lcemd_server_stop", "lcemd_check_histograms"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load_library()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert set(_declared_functions()) == set(L._SIGS), "binding and header disagree"
+    assert lib.lcemd_version() == 1
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+
+    def const(name):
+        m = re.search(r"#define\s+%s\s+\(?(-?0x[0-9a-fA-F]+|-?\d+)u?\)?" % name, text)
+        return int(m.group(1), 0)
+
+    assert const("LCEMD_E_BAD_CSR") == L.E_BAD_CSR
+    assert const("LCEMD_E_NO_DEVICE") == L.E_NO_DEVICE
+    assert const("LCEMD_ICT") == L.ICT and const("LCEMD_SYM") == L.SYM
+    assert const("LCEMD_PTR_DEVICE") == L.PTR_DEVICE
+    assert const("LCEMD_MAX_HIST") == L.MAX_HIST and const("LCEMD_MAX_L") == L.MAX_L
+
+
+def _has_gpu():
+    try:
+        import torch
+
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_create_without_device_reports_no_device():
+    with pytest.raises(L.LcemdError) as e:
+        L.Context(0)
+    assert e.value.code == L.E_NO_DEVICE
+
+
+def _good():
+    ptr = np.array([0, 2, 5], dtype=np.int64)
+    col = np.array([1, 4, 0, 2, 3], dtype=np.int32)
+    val = np.array([0.25, 0.75, 0.2, 0.3, 0.5], dtype=np.float32)
+    return ptr, col, val
+
+
+def test_validation_accepts_canonical_csr():
+    rc, msg = L.check_histograms(*_good(), v=5)
+    assert rc == L.OK and msg == ""
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p, c, v: (np.array([1, 2, 5]), c, v), L.E_BAD_CSR),          # rowptr[0] != 0
+    (lambda p, c, v: (np.array([0, 2, 2]), c, v), L.E_BAD_CSR),          # empty row
+    (lambda p, c, v: (p, np.array([4, 1, 0, 2, 3]), v), L.E_BAD_CSR),    # unsorted columns
+    (lambda p, c, v: (p, np.array([1, 1, 0, 2, 3]), v), L.E_BAD_CSR),    # duplicate column
+    (lambda p, c, v: (p, np.array([1, 4, 0, 2, 9]), v), L.E_BAD_CSR),    # column >= v
+    (lambda p, c, v: (p, c, np.array([0.25, 0.75, 0.0, 0.5, 0.5])), L.E_BAD_CSR),   # explicit zero
+    (lambda p, c, v: (p, c, np.array([0.25, 0.75, np.nan, 0.3, 0.7])), L.E_BAD_CSR),  # NaN
+    (lambda p, c, v: (p, c, np.array([0.25, 0.70, 0.2, 0.3, 0.5])), L.E_BAD_CSR),   # sum != 1
+])
+def test_validation_rejects(mutate, code):
+    p, c, v = mutate(*_good())
+    rc, msg = L.check_histograms(p, c, v, v=5)
+    assert rc == code and msg
+
+
+def test_validation_row_sum_optional_and_capacity():
+    p, c, v = _good()
+    v2 = v * 2
+    assert L.check_histograms(p, c, v2, v=5, require_normalized=False)[0] == L.OK
+    assert L.check_histograms(p, c, v2, v=5, require_normalized=True)[0] == L.E_BAD_CSR
+    h = L.MAX_HIST + 1
+    ptr = np.array([0, h], dtype=np.int64)
+    col = np.arange(h, dtype=np.int32)
+    val = np.full(h, 1.0 / h, dtype=np.float32)
+    assert L.check_histograms(ptr, col, val, v=h)[0] == L.E_CAPACITY
+
+
+def test_opts_layout_matches_header():
+    assert ctypes.sizeof(L.lcemd_opts) == 8 * 4
+    assert ctypes.sizeof(L.lcemd_query) == 8 * 3 + 8 + 8
