@@ -306,9 +306,43 @@ int check_opts(lcemd_ctx* c, const lcemd_opts* o) {
     return fail(c, LCEMD_E_INVALID_ARG, "ACT needs 1 <= k <= %d (got %d)", LCEMD_MAX_K, o->k);
   if (o->direction < LCEMD_D2Q || o->direction > LCEMD_SYM) return fail(c, LCEMD_E_INVALID_ARG, "unknown direction %d", o->direction);
   if (o->precision < LCEMD_FP32 || o->precision > LCEMD_FP8) return fail(c, LCEMD_E_INVALID_ARG, "unknown precision %d", o->precision);
-  if (o->precision != LCEMD_FP32) return fail(c, LCEMD_E_UNSUPPORTED, "only LCEMD_FP32 phase 1 is built");
+  if (o->precision == LCEMD_FP8) return fail(c, LCEMD_E_UNSUPPORTED, "LCEMD_FP8 phase 1 is not built");
   for (int i = 0; i < 3; ++i)
     if (o->reserved[i]) return fail(c, LCEMD_E_INVALID_ARG, "reserved option fields must be 0");
+  return LCEMD_OK;
+}
+
+constexpr int kMargin = 8;  // over-selection for approximate (bf16/fp8) keys
+
+int pow2ceil(int x) {
+  int p = 2;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+int ensure_precision(lcemd_ctx* c, int prec) {
+  if (prec == LCEMD_BF16 && !c->Vb) {
+    int rc = dalloc(c, c->Vb, (size_t)c->v * c->m_pad, "bfloat16 embeddings");
+    if (rc) return rc;
+    HIPCHK(c, launch_make_bf16(c->V, c->v * (int64_t)c->m_pad, c->Vb, c->stream));
+  }
+  return LCEMD_OK;
+}
+
+// Launch phase 1: rows of `a` may need up to `depth` list entries; the
+// streaming kernel handles depth <= 64, deeper rows go to the kernel that
+// keeps a whole row of keys in LDS (float32 keys).
+int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hmax) {
+  if (depth <= 64) {
+    const int margin = prec == LCEMD_FP32 ? 0 : kMargin;
+    const int KL = pow2ceil(std::min(depth + margin, 64));
+    a.KT_margin = margin;
+    a.Vb = c->Vb;
+    HIPCHK(c, launch_phase1_fast(a, mode, KL, prec, c->stream));
+  } else {
+    a.KT_margin = 0;
+    HIPCHK(c, launch_phase1_deep(a, mode, seg_hmax, PREC_F32, c->stream));
+  }
   return LCEMD_OK;
 }
 
@@ -375,7 +409,7 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     a.overflow = ovf;
     int64_t H = Q.hptr[q0 + nq] - Q.hptr[q0];
     if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)c->v_used * (double)H * (double)c->m))) return rc;
-    HIPCHK(c, launch_phase1(a, P1_TABLE, Q.hmax, PREC_F32, c->stream));
+    if ((rc = p1_launch(c, a, P1_TABLE, o->precision, KT, Q.hmax))) return rc;
     if ((rc = prof_end(c))) return rc;
     if (o->method == LCEMD_ICT && KT < Q.hmax) {
       int h_ovf = 0;
@@ -402,13 +436,23 @@ int run_pairs(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, P1Args a, float*
   float* partial;
   int rc;
   if ((rc = wsget(c, "partial", (size_t)a.npairs * rb_max, partial))) return rc;
+  int* ovf;
+  if ((rc = wsget(c, "ovf_pair", 1, ovf))) return rc;
   a.rb_max = rb_max;
   a.partial = partial;
+  a.overflow = ovf;
+  const int depth = table_depth(o, c->db_hmax);
+  HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
   if ((rc = prof_begin(c, "phase1_pair_q2d", (double)a.npairs))) return rc;
-  HIPCHK(c, launch_phase1(a, P1_PAIR, c->db_hmax, PREC_F32, c->stream));
+  if ((rc = p1_launch(c, a, P1_PAIR, o->precision, depth, c->db_hmax))) return rc;
   if ((rc = prof_end(c))) return rc;
+  if (o->method == LCEMD_ICT && depth < c->db_hmax) {
+    int h_ovf = 0;
+    HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h_ovf && (rc = p1_launch(c, a, P1_PAIR, o->precision, c->db_hmax, c->db_hmax))) return rc;
+  }
   HIPCHK(c, launch_pair_reduce(partial, a.npairs, rb_max, out, out_ld, per_row, c->stream));
-  (void)o;
   return LCEMD_OK;
 }
 
@@ -516,7 +560,7 @@ int lcemd_load_embeddings(lcemd_ctx* c, const float* V, int64_t v, int32_t m, ui
   }
   free_db(c);
   free_emb(c);
-  const int m_pad = ((m + kKChunk - 1) / kKChunk) * kKChunk;
+  const int m_pad = ((m + 63) / 64) * 64;  // one 128-byte bf16 slice = 64 dims
   int rc;
   if ((rc = dalloc(c, c->V, (size_t)v * m_pad, "embeddings"))) return rc;
   if ((rc = dalloc(c, c->vnorm, (size_t)v, "row norms"))) return rc;
@@ -664,6 +708,7 @@ int lcemd_distances(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, flo
   prof_reset(c);
   QDev Q;
   if ((rc = stage_query(c, q, Q))) return rc;
+  if ((rc = ensure_precision(c, o->precision))) return rc;
   const int64_t n = c->n;
   float* dout = out;
   if (!Q.device && (rc = wsget(c, "dist_out", (size_t)Q.B * n, dout))) return rc;
@@ -700,6 +745,7 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
   prof_reset(c);
   QDev Q;
   if ((rc = stage_query(c, q, Q))) return rc;
+  if ((rc = ensure_precision(c, o->precision))) return rc;
   const int64_t B = Q.B;
   if (o->exclude_self >= 0 && o->exclude_self + B > n)
     return fail(c, LCEMD_E_INVALID_ARG, "exclude_self + B exceeds the database size");
@@ -796,7 +842,8 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
   c->err.clear();
   if (!o) return fail(c, LCEMD_E_INVALID_ARG, "opts must not be NULL");
   if (o->k < 1 || o->k > LCEMD_MAX_K) return fail(c, LCEMD_E_INVALID_ARG, "need 1 <= k <= %d", LCEMD_MAX_K);
-  if (o->precision != LCEMD_FP32) return fail(c, LCEMD_E_UNSUPPORTED, "only LCEMD_FP32 phase 1 is built");
+  if (o->precision < LCEMD_FP32 || o->precision > LCEMD_BF16)
+    return fail(c, LCEMD_E_UNSUPPORTED, "tables: precision must be LCEMD_FP32 or LCEMD_BF16");
   if (!S || !Z || !W) return fail(c, LCEMD_E_INVALID_ARG, "S/Z/W must not be NULL");
   (void)hipSetDevice(c->device);
   prof_reset(c);
@@ -818,7 +865,8 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
   a.Z = dZ;
   a.W = dW;
   if (Q.B > 65535) return fail(c, LCEMD_E_CAPACITY, "tables: at most 65535 queries per call");
-  HIPCHK(c, launch_phase1(a, P1_TABLE_FULL, Q.hmax, PREC_F32, c->stream));
+  if ((rc = ensure_precision(c, o->precision))) return rc;
+  if ((rc = p1_launch(c, a, P1_TABLE_FULL, o->precision, o->k, Q.hmax))) return rc;
   if (!Q.device) {
     HIPCHK(c, hipMemcpyAsync(S, dS, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(Z, dZ, sizeof(float) * total, hipMemcpyDeviceToHost, c->stream));

@@ -44,6 +44,7 @@ struct P1Args {
   int method;             // LCEMD_RWMD / OMR / ACT / ICT
   int k;                  // ACT k
   int KT;                 // table stride (entries per table row)
+  int KT_margin;          // extra candidates kept for the exact re-sort (bf16/fp8 keys)
   // database
   int64_t n;
   const int64_t* xptr;    // [n+1]
@@ -77,7 +78,8 @@ struct P1Args {
 };
 
 // kernel launchers (each in the translation unit of its kernel)
-hipError_t launch_phase1(const P1Args& a, int mode, int hmax, int prec, hipStream_t s);
+hipError_t launch_phase1_deep(const P1Args& a, int mode, int hmax, int prec, hipStream_t s);
+hipError_t launch_phase1_fast(const P1Args& a, int mode, int KT, int prec, hipStream_t s);
 hipError_t launch_pair_reduce(const float* partial, int64_t npairs, int rb_max, float* out,
                               int64_t out_ld, int64_t per_row, hipStream_t s);
 hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const float2* ZW,

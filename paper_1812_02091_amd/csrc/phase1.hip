@@ -311,7 +311,7 @@ static hipError_t launch_mode(const P1Args& a, int hmax, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_phase1(const P1Args& a, int mode, int hmax, int prec, hipStream_t s) {
+hipError_t launch_phase1_deep(const P1Args& a, int mode, int hmax, int prec, hipStream_t s) {
   if (prec != PREC_F32) return hipErrorInvalidValue;
   switch (mode) {
     case P1_TABLE: return launch_mode<P1_TABLE>(a, hmax, s);

@@ -259,3 +259,39 @@ def test_invalid_query_rejected_before_device_work(tiny, L):
     with pytest.raises(L.LcemdError) as e:
         ctx.distances(*_q(w), method="act", k=0)
     assert e.value.code == L.E_INVALID_ARG
+
+
+# ---------------------------------------------------------------------------
+# bfloat16 phase-1 contraction: candidates ranked on bf16 keys with a margin,
+# every listed distance recomputed exactly in float32 and re-sorted
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_tables_bf16_image_exact(image_small, k):
+    """Grid coordinates <= 27 are exact in bfloat16 and their products sum
+    exactly in float32, so even bf16 keys give the exact tie-broken sets."""
+    w, ctx, orc = image_small
+    say(f"[gpu] bf16 tables image k={k}")
+    S, Z, W = ctx.tables(*_q(w), k=k, precision="bf16")
+    for b in range(w.queries.n):
+        qc, qw = w.queries.row(b)
+        So, Zo, Wo, R = orc.tables(qc, qw, k)
+        assert np.array_equal(S[b].astype(np.int64), So), b
+        assert np.allclose(Z[b], Zo, rtol=1e-6, atol=0), b
+
+
+@pytest.mark.parametrize("method,k", [("rwmd", 1), ("omr", 1), ("act", 3), ("act", 16), ("ict", 1)])
+@pytest.mark.parametrize("wl", ["tiny", "text"])
+def test_distances_bf16(tiny, text_small, method, k, wl):
+    w, ctx, orc = tiny if wl == "tiny" else text_small
+    say(f"[gpu] bf16 distances {wl} {method} k={k} sym")
+    g = ctx.distances(*_q(w), method=method, k=k, direction="sym", precision="bf16")
+    o = _oracle_matrix(orc, w, method, k, "sym")
+    P.assert_distances(g, o, f"bf16 {wl} {method}{k}")
+
+
+def test_topl_bf16_text(text_small):
+    w, ctx, orc = text_small
+    say("[gpu] bf16 top-16 text act8 sym")
+    idx, dist = ctx.topl(*_q(w), 16, method="act", k=8, direction="sym", precision="bf16")
+    o = _oracle_matrix(orc, w, "act", 8, "sym")
+    for b in range(w.queries.n):
+        P.check_topl(idx[b], dist[b], o[b], 16, f"b={b}")
