@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -57,6 +58,9 @@ struct lcemd_ctx {
   // scratch, grow-only
   std::map<std::string, DevBuf> ws;
   size_t table_budget = size_t(12) << 30;
+  int force_kernel = 0;   // test hook (LCEMD_FORCE_KERNEL): 1 = skip the 128-row kernel, 2 = deep kernel
+  int64_t fallbacks = 0;  // tiles redone with float32 keys / deeper lists
+  int64_t fixed_rows = 0; // bf16 table rows redone exactly one by one
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
@@ -313,6 +317,7 @@ int check_opts(lcemd_ctx* c, const lcemd_opts* o) {
 }
 
 constexpr int kMargin = 8;  // over-selection for approximate (bf16/fp8) keys
+constexpr int kFixCap = 1 << 20;  // rows per launch that may be redone exactly
 
 int pow2ceil(int x) {
   int p = 2;
@@ -329,18 +334,32 @@ int ensure_precision(lcemd_ctx* c, int prec) {
   return LCEMD_OK;
 }
 
-// Launch phase 1: rows of `a` may need up to `depth` list entries; the
-// streaming kernel handles depth <= 64, deeper rows go to the kernel that
-// keeps a whole row of keys in LDS (float32 keys).
-int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hmax) {
-  if (depth <= 64) {
-    const int margin = prec == LCEMD_FP32 ? 0 : kMargin;
+// Launch phase 1: rows of `a` may need up to `depth` list entries.  Lists of
+// up to 32 entries (with the bf16 margin) run on the 128-row kernel, up to
+// 64 on the 64-row streaming kernel, deeper rows on the kernel that keeps a
+// whole row of keys in LDS (float32 keys).  Pair mode: a.rb_max is set to
+// the row-block count of the chosen kernel for queries of up to row_hmax
+// words (callers size `partial` for 64-row blocks, the largest count).
+int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hmax,
+              int row_hmax) {
+  // bf16 keys carry an exactness certificate only on the 128-row kernel;
+  // deeper lists use float32 keys
+  if (prec != LCEMD_FP32 && (depth + kMargin > 32 || c->force_kernel || mode == P1_PAIR)) prec = LCEMD_FP32;
+  const int margin = prec == LCEMD_FP32 ? 0 : kMargin;
+  a.Vb = c->Vb;
+  if (depth + margin <= 32 && !c->force_kernel) {
+    const int KL = pow2ceil(depth + margin);
+    a.KT_margin = margin;
+    a.rb_max = (row_hmax + phase1_wide_rows() - 1) / phase1_wide_rows();
+    HIPCHK(c, launch_phase1_wide(a, mode, KL, prec, c->stream));
+  } else if (depth <= 64 && c->force_kernel != 2) {
     const int KL = pow2ceil(std::min(depth + margin, 64));
     a.KT_margin = margin;
-    a.Vb = c->Vb;
+    a.rb_max = (row_hmax + kRows - 1) / kRows;
     HIPCHK(c, launch_phase1_fast(a, mode, KL, prec, c->stream));
   } else {
     a.KT_margin = 0;
+    a.rb_max = (row_hmax + kRows - 1) / kRows;
     HIPCHK(c, launch_phase1_deep(a, mode, seg_hmax, PREC_F32, c->stream));
   }
   return LCEMD_OK;
@@ -389,6 +408,7 @@ P1Args base_args(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o) {
 // out[b * ld + u].
 int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
   int KT = table_depth(o, Q.hmax);
+  int prec = o->precision;
   const size_t per_q = (size_t)c->v_used * sizeof(float2);
   int* ovf;
   int rc;
@@ -407,16 +427,39 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     a.nq = nq;
     a.ZW = ZW;
     a.overflow = ovf;
+    int* fixc = nullptr;
+    if (prec != LCEMD_FP32) {
+      if ((rc = wsget(c, "fix_count", 1, fixc)) || (rc = wsget(c, "fix_list", kFixCap, a.fix_list))) return rc;
+      HIPCHK(c, hipMemsetAsync(fixc, 0, sizeof(int), c->stream));
+      a.fix_count = fixc;
+      a.fix_cap = kFixCap;
+    }
     int64_t H = Q.hptr[q0 + nq] - Q.hptr[q0];
     if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)c->v_used * (double)H * (double)c->m))) return rc;
-    if ((rc = p1_launch(c, a, P1_TABLE, o->precision, KT, Q.hmax))) return rc;
+    if ((rc = p1_launch(c, a, P1_TABLE, prec, KT, Q.hmax, Q.hmax))) return rc;
     if ((rc = prof_end(c))) return rc;
-    if (o->method == LCEMD_ICT && KT < Q.hmax) {
-      int h_ovf = 0;
+    if ((o->method == LCEMD_ICT && KT < Q.hmax) || prec != LCEMD_FP32) {
+      int h_ovf = 0, h_fix = 0;
       HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      if (fixc) HIPCHK(c, hipMemcpyAsync(&h_fix, fixc, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
-      if (h_ovf) {  // some row needs a deeper table: widen and redo this tile
-        KT = Q.hmax;
+      if (!h_ovf && h_fix > 0) {
+        if ((rc = prof_begin(c, "fix_rows", (double)h_fix))) return rc;
+        HIPCHK(c, launch_fix_rows(a, P1_TABLE, h_fix, c->stream));
+        if ((rc = prof_end(c))) return rc;
+        c->fixed_rows += h_fix;
+        HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+      }
+      if (h_ovf) {
+        // a row needed more list entries than the kernel keeps: redo the tile
+        // with float32 keys, and for ICT with full-depth tables
+        if (prec != LCEMD_FP32) {
+          prec = LCEMD_FP32;
+          ++c->fallbacks;
+        } else {
+          KT = Q.hmax;
+        }
         continue;
       }
     }
@@ -425,6 +468,7 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     HIPCHK(c, launch_phase2(c->xptr, c->xcv, c->n, ZW, c->v_used, KT, nq, out + q0 * ld, ld, c->stream));
     if ((rc = prof_end(c))) return rc;
     q0 += nq;
+    prec = o->precision;
   }
   return LCEMD_OK;
 }
@@ -432,27 +476,30 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
 // Q2D for an explicit list of pairs or candidates (see P1Args).
 int run_pairs(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, P1Args a, float* out,
               int64_t out_ld, int64_t per_row) {
-  const int rb_max = (Q.hmax + kRows - 1) / kRows;
+  const int rb_cap = (Q.hmax + kRows - 1) / kRows;
   float* partial;
   int rc;
-  if ((rc = wsget(c, "partial", (size_t)a.npairs * rb_max, partial))) return rc;
+  if ((rc = wsget(c, "partial", (size_t)a.npairs * rb_cap, partial))) return rc;
   int* ovf;
   if ((rc = wsget(c, "ovf_pair", 1, ovf))) return rc;
-  a.rb_max = rb_max;
   a.partial = partial;
   a.overflow = ovf;
   const int depth = table_depth(o, c->db_hmax);
   HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
   if ((rc = prof_begin(c, "phase1_pair_q2d", (double)a.npairs))) return rc;
-  if ((rc = p1_launch(c, a, P1_PAIR, o->precision, depth, c->db_hmax))) return rc;
+  if ((rc = p1_launch(c, a, P1_PAIR, o->precision, depth, c->db_hmax, Q.hmax))) return rc;
   if ((rc = prof_end(c))) return rc;
-  if (o->method == LCEMD_ICT && depth < c->db_hmax) {
+  if ((o->method == LCEMD_ICT && depth < c->db_hmax) || o->precision != LCEMD_FP32) {
     int h_ovf = 0;
     HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (h_ovf && (rc = p1_launch(c, a, P1_PAIR, o->precision, c->db_hmax, c->db_hmax))) return rc;
+    if (h_ovf) {
+      ++c->fallbacks;
+      const int d2 = o->method == LCEMD_ICT ? c->db_hmax : depth;
+      if ((rc = p1_launch(c, a, P1_PAIR, LCEMD_FP32, d2, c->db_hmax, Q.hmax))) return rc;
+    }
   }
-  HIPCHK(c, launch_pair_reduce(partial, a.npairs, rb_max, out, out_ld, per_row, c->stream));
+  HIPCHK(c, launch_pair_reduce(partial, a.npairs, a.rb_max, out, out_ld, per_row, c->stream));
   return LCEMD_OK;
 }
 
@@ -519,6 +566,7 @@ int lcemd_create(lcemd_ctx** out, int device) {
     return LCEMD_E_HIP;
   }
   c->stream = c->own_stream;
+  if (const char* fk = getenv("LCEMD_FORCE_KERNEL")) c->force_kernel = atoi(fk);
   *out = c;
   return LCEMD_OK;
 }
@@ -688,6 +736,13 @@ int64_t lcemd_used_vocab(lcemd_ctx* c, int32_t* ids) {
 int lcemd_profile(lcemd_ctx* c, int enable) {
   if (!c) return LCEMD_E_INVALID_ARG;
   c->prof = enable != 0;
+  return LCEMD_OK;
+}
+
+int lcemd_counters(lcemd_ctx* c, int64_t* fallback_tiles, int64_t* exact_rows) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  if (fallback_tiles) *fallback_tiles = c->fallbacks;
+  if (exact_rows) *exact_rows = c->fixed_rows;
   return LCEMD_OK;
 }
 
@@ -866,7 +921,31 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
   a.W = dW;
   if (Q.B > 65535) return fail(c, LCEMD_E_CAPACITY, "tables: at most 65535 queries per call");
   if ((rc = ensure_precision(c, o->precision))) return rc;
-  if ((rc = p1_launch(c, a, P1_TABLE_FULL, o->precision, o->k, Q.hmax))) return rc;
+  int* ovf;
+  int* fixc;
+  if ((rc = wsget(c, "ovf", 1, ovf)) || (rc = wsget(c, "fix_count", 1, fixc)) ||
+      (rc = wsget(c, "fix_list", kFixCap, a.fix_list)))
+    return rc;
+  HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
+  HIPCHK(c, hipMemsetAsync(fixc, 0, sizeof(int), c->stream));
+  a.overflow = ovf;
+  a.fix_count = fixc;
+  a.fix_cap = kFixCap;
+  if ((rc = p1_launch(c, a, P1_TABLE_FULL, o->precision, o->k, Q.hmax, Q.hmax))) return rc;
+  if (o->precision != LCEMD_FP32) {
+    int h_ovf = 0, h_fix = 0;
+    HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&h_fix, fixc, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h_ovf) {  // redo everything with float32 keys
+      HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
+      if ((rc = p1_launch(c, a, P1_TABLE_FULL, LCEMD_FP32, o->k, Q.hmax, Q.hmax))) return rc;
+      ++c->fallbacks;
+    } else if (h_fix > 0) {
+      HIPCHK(c, launch_fix_rows(a, P1_TABLE_FULL, h_fix, c->stream));
+      c->fixed_rows += h_fix;
+    }
+  }
   if (!Q.device) {
     HIPCHK(c, hipMemcpyAsync(S, dS, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(Z, dZ, sizeof(float) * total, hipMemcpyDeviceToHost, c->stream));

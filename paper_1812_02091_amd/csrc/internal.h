@@ -75,11 +75,17 @@ struct P1Args {
   float* W;
   float* partial;         // P1_PAIR: [npairs][rb_max]
   int* overflow;          // set to 1 when a row needed more than KT entries
+  int* fix_count;         // bf16 table modes: rows whose exactness certificate failed ...
+  int64_t* fix_list;      // ... are appended here (flat table row index) for k_fix_rows
+  int fix_cap;
 };
 
 // kernel launchers (each in the translation unit of its kernel)
 hipError_t launch_phase1_deep(const P1Args& a, int mode, int hmax, int prec, hipStream_t s);
 hipError_t launch_phase1_fast(const P1Args& a, int mode, int KT, int prec, hipStream_t s);
+hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, hipStream_t s);
+int phase1_wide_rows();
+hipError_t launch_fix_rows(const P1Args& a, int mode, int count, hipStream_t s);
 hipError_t launch_pair_reduce(const float* partial, int64_t npairs, int rb_max, float* out,
                               int64_t out_ld, int64_t per_row, hipStream_t s);
 hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const float2* ZW,

@@ -1,0 +1,715 @@
+// Phase 1 of LC-ACT (Sec. 4, Phase 1), wide variant: 128 rows per
+// workgroup and up to 128 columns per MFMA pass.
+//
+// Contraction: wave w owns rows [32w, 32w+32).  Its row operand (32 rows x
+// one 128-byte slice of dims) is read straight from global memory into
+// registers -- no other wave needs it -- while the column slice (128
+// columns) is staged once in LDS for all four waves.  Each wave keeps four
+// 32x32 accumulators (one per 32-column tile) and issues them interleaved.
+// The next slice is prefetched into registers during the MFMAs, so a slice
+// costs one LDS store and two barriers.
+//
+// Selection: after a pass the keys |c|^2 - 2 <v, c> go to LDS 64 columns at
+// a time and two lanes per row merge them into the row's sorted candidate
+// list (packed (key, position); position breaks ties), cut at k_eff = min(k,
+// h) (Alg. 3; 1 for RWMD, 2 for OMR) or as soon as the listed capacities
+// reach the row's bound (Lemma 1/2: no transfer of at most that much mass
+// passes this point).
+//
+// Exact distances: float32 keys -- the list distance is |v|^2 + key unless
+// cancellation could bite (below a quarter of |v|^2 + |c|^2), where it is
+// recomputed by direct differences.  bfloat16 keys -- every bf16-rounded
+// product is within 2^-8 of the exact one, so a key is off by at most
+// 2^-7 * 1.0625 * |v||c| (float32 accumulation included for m <= 4096);
+// the list therefore keeps, past the cut, every candidate whose key is
+// within 2^-6 * 1.07 * |v| * max|c| of the cut key: in exact order nothing
+// outside that band can precede the cut.  All listed candidates are then
+// recomputed exactly in float32 (the segment's vectors staged through LDS
+// 8 dims at a time), re-sorted and cut again.
+#include "internal.h"
+
+namespace lcemd {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int kWR = 128;        // rows per workgroup
+constexpr int kWC = 128;        // columns per MFMA pass
+constexpr int kStride = 144;    // bytes per staged column slice (128 + 16 pad)
+constexpr int kCK = 66;         // floats per key row (64 columns + 2 pad)
+constexpr int kQD = 8;          // dims per exact-recompute chunk
+constexpr int kQS = 12;         // floats per staged segment vector (8 dims + 4 pad)
+constexpr int kSeg = LCEMD_MAX_HIST;
+constexpr int kGroupW = 8;      // queries per tile group (table modes)
+constexpr float kGuardW = 0.25f;
+constexpr float kBandBF16 = 0.015625f * 1.07f;  // 2^-6 * 1.07
+
+__device__ __forceinline__ uint32_t w_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ uint64_t w_pack(float f, uint32_t pos) {
+  return ((uint64_t)w_bits(f) << 32) | (uint64_t)pos;
+}
+__device__ __forceinline__ float w_unpack(uint64_t k) {
+  const uint32_t o = (uint32_t)(k >> 32);
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+__device__ __forceinline__ uint64_t w_shfl1(uint64_t v) {
+  int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  lo = __shfl_xor(lo, 1);
+  hi = __shfl_xor(hi, 1);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+__device__ __forceinline__ float w_exact_d2(const float* __restrict__ V, int m_pad, int a, int b) {
+  const float4* x = (const float4*)(V + (size_t)a * m_pad);
+  const float4* y = (const float4*)(V + (size_t)b * m_pad);
+  float s = 0.f;
+  const int n4 = m_pad >> 2;
+  for (int d = 0; d < n4; ++d) {
+    const float4 p = x[d], q = y[d];
+    const float e0 = p.x - q.x, e1 = p.y - q.y, e2 = p.z - q.z, e3 = p.w - q.w;
+    s = fmaf(e0, e0, s);
+    s = fmaf(e1, e1, s);
+    s = fmaf(e2, e2, s);
+    s = fmaf(e3, e3, s);
+  }
+  return s;
+}
+
+// One staged slice on NT 32-column tiles (NT fixed at compile time so the
+// MFMAs issue back to back without branches).
+template <int NT>
+__device__ __forceinline__ void slice_f32(floatx16 (&acc)[4], const uint4 (&a_cur)[4],
+                                          const unsigned char* st, int li, int lh) {
+  // lane half lh supplies dims [16 lh, 16 lh + 16) of the 32-dim slice
+  const float* af = (const float*)a_cur;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float4 bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      bv[t] = *(const float4*)(st + (32 * t + li) * kStride + lh * 64 + j * 16);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[4 * j + 0], bv[t].x, acc[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[4 * j + 1], bv[t].y, acc[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[4 * j + 2], bv[t].z, acc[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[4 * j + 3], bv[t].w, acc[t], 0, 0, 0);
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void slice_bf16(floatx16 (&acc)[4], const uint4 (&a_cur)[4],
+                                           const unsigned char* st, int li, int lh) {
+  // lane half lh supplies dims [32 lh + 8 s, +8) of the 64-dim slice
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(&a_cur[s]);
+    bf16x8 bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bv[t] = *(const bf16x8*)(st + (32 * t + li) * kStride + lh * 64 + s * 16);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[t], acc[t], 0, 0, 0);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void slice_mfma(int ntile, floatx16 (&acc)[4], const uint4 (&a_cur)[4],
+                                           const unsigned char* st, int li, int lh) {
+  if constexpr (PREC == PREC_F32) {
+    switch (ntile) {
+      case 1: slice_f32<1>(acc, a_cur, st, li, lh); break;
+      case 2: slice_f32<2>(acc, a_cur, st, li, lh); break;
+      case 3: slice_f32<3>(acc, a_cur, st, li, lh); break;
+      default: slice_f32<4>(acc, a_cur, st, li, lh); break;
+    }
+  } else {
+    switch (ntile) {
+      case 1: slice_bf16<1>(acc, a_cur, st, li, lh); break;
+      case 2: slice_bf16<2>(acc, a_cur, st, li, lh); break;
+      case 3: slice_bf16<3>(acc, a_cur, st, li, lh); break;
+      default: slice_bf16<4>(acc, a_cur, st, li, lh); break;
+    }
+  }
+}
+
+template <int KL, int PREC>
+struct WideSmem {
+  union {
+    unsigned char st[kWC * kStride];  // staged column slice
+    float ck[kWR * kCK];              // keys of 64 columns of a pass
+    float qs[PREC == PREC_F32 ? 1 : kSeg * kQS];  // segment vectors, 8 dims (exact recompute)
+    float zb[kWR * (KL + 1)];         // exact squared distances of the lists
+  } u;
+  uint64_t lst[2][kWR * (KL + 1)];  // row stride KL + 1 spreads rows over LDS banks
+  int cid[kSeg];
+  float cap[kSeg];
+  float qn[kSeg];
+  int rid[kWR];
+  float rbound[kWR];
+  float rvn[kWR];
+  int rlen[kWR];
+  float rcost[kWR];
+  float rdrop[kWR];  // smallest key dropped because the list was full
+  int rcut[kWR];     // the last merge reached k_eff or the row's bound
+  float qmax;
+};
+
+}  // namespace
+
+template <int MODE, int KL, int PREC>
+__global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a) {
+  using Sm = WideSmem<KL, PREC>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Sm& sm = *reinterpret_cast<Sm*>(smem_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  // ---------------- task decode ----------------
+  int nrows = 0, h = 0;
+  int64_t out_row0 = 0, pidx = 0;
+  int rb = 0;
+  if constexpr (MODE == P1_PAIR) {
+    pidx = blockIdx.x;
+    rb = blockIdx.y;
+    int64_t b, u;
+    if (a.cand) {
+      const int64_t qi = pidx / a.cand_use, c = pidx % a.cand_use;
+      b = a.qlist ? (int64_t)a.qlist[qi] : qi;
+      u = (int64_t)(uint32_t)a.cand[qi * a.cand_ld + c];
+    } else if (a.pair_q) {
+      b = a.pair_q[pidx];
+      u = a.pair_u[pidx];
+    } else {
+      b = a.q0 + pidx / a.n;
+      u = pidx % a.n;
+    }
+    const int64_t qs0 = a.qptr[b];
+    const int hq = (int)(a.qptr[b + 1] - qs0);
+    nrows = min(kWR, hq - rb * kWR);
+    if (nrows <= 0 || u < 0 || u >= a.n) {
+      if (tid == 0) a.partial[pidx * a.rb_max + rb] = 0.f;
+      return;
+    }
+    if (tid < kWR) {
+      const bool ok = tid < nrows;
+      const int w = ok ? a.qcol[qs0 + rb * kWR + tid] : 0;
+      sm.rid[tid] = w;
+      sm.rbound[tid] = ok ? a.qval[qs0 + rb * kWR + tid] : 0.f;
+      sm.rvn[tid] = a.vnorm[w];
+      sm.rlen[tid] = 0;
+      sm.rdrop[tid] = INFINITY;
+    }
+    const int64_t s0 = a.xptr[u];
+    h = (int)(a.xptr[u + 1] - s0);
+    for (int c = tid; c < h; c += kThreads) {
+      const int w = a.xcol[s0 + c];
+      sm.cid[c] = w;
+      sm.cap[c] = __int_as_float(a.xcv[s0 + c].y);
+      sm.qn[c] = a.vnorm[w];
+    }
+  } else {
+    const int64_t nrb = (a.v_used + kWR - 1) / kWR;
+    const int64_t ngroups = (a.nq + kGroupW - 1) / kGroupW;
+    const int64_t total = ngroups * nrb * kGroupW;
+    const int64_t per = (int64_t)gridDim.x / 8;
+    const int64_t work = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (work >= total) return;
+    const int64_t qin = work % kGroupW, t = work / kGroupW;
+    const int64_t rblk = t % nrb, g = t / nrb;
+    const int64_t qi = g * kGroupW + qin;
+    if (qi >= a.nq) return;
+    const int64_t r0 = rblk * kWR;
+    const int64_t b = a.q0 + qi;
+    nrows = (int)min((int64_t)kWR, a.v_used - r0);
+    out_row0 = qi * a.v_used + r0;
+    if (tid < kWR) {
+      const bool ok = tid < nrows;
+      const int w = ok ? a.used[r0 + tid] : 0;
+      sm.rid[tid] = w;
+      sm.rbound[tid] = ok ? (MODE == P1_TABLE ? a.xmax[r0 + tid] : INFINITY) : 0.f;
+      sm.rvn[tid] = a.vnorm[w];
+      sm.rlen[tid] = 0;
+      sm.rdrop[tid] = INFINITY;
+    }
+    const int64_t s0 = a.qptr[b];
+    h = (int)(a.qptr[b + 1] - s0);
+    for (int c = tid; c < h; c += kThreads) {
+      const int w = a.qcol[s0 + c];
+      sm.cid[c] = w;
+      sm.cap[c] = a.qval[s0 + c];
+      sm.qn[c] = a.vnorm[w];
+    }
+  }
+  if (tid == 0) sm.qmax = 0.f;
+  __syncthreads();
+  if (PREC != PREC_F32 && tid < 64) {
+    float mx = 0.f;
+    for (int c = tid; c < h; c += 64) mx = fmaxf(mx, sm.qn[c]);
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (tid == 0) sm.qmax = sqrtf(mx);
+  }
+
+  int kef;
+  if constexpr (MODE == P1_TABLE_FULL) {
+    kef = min(a.k, h);
+  } else {
+    if (a.method == LCEMD_ICT) kef = h;
+    else if (a.method == LCEMD_OMR) kef = min(2, h);
+    else if (a.method == LCEMD_RWMD) kef = 1;
+    else kef = min(a.k, h);
+  }
+  constexpr bool kCapStop = MODE != P1_TABLE_FULL;
+
+  // ---------------- contraction ----------------
+  const unsigned char* base = PREC == PREC_F32 ? (const unsigned char*)a.V : (const unsigned char*)a.Vb;
+  const size_t rowbytes = (size_t)a.m_pad * (PREC == PREC_F32 ? 4 : 2);
+  const int nsl = (int)(rowbytes / 128);
+  const int li = lane & 31, lh = lane >> 5;
+  const int arow = 32 * wave + li;
+  const bool arow_ok = arow < nrows;
+  const unsigned char* aptr = base + (size_t)sm.rid[arow] * rowbytes + lh * 64;
+
+  uint4 a_cur[4], a_nxt[4], b_nxt[4];
+  auto load_a = [&](int sl) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a_nxt[i] = arow_ok ? *(const uint4*)(aptr + sl * 128 + i * 16) : make_uint4(0, 0, 0, 0);
+  };
+  auto load_b = [&](int c0, int sl) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int f = tid + it * kThreads;
+      const int c = f >> 3, q = f & 7;
+      const int cc = c0 + c;
+      b_nxt[it] = cc < h ? *(const uint4*)(base + (size_t)sm.cid[cc] * rowbytes + sl * 128 + q * 16)
+                         : make_uint4(0, 0, 0, 0);
+    }
+  };
+
+  const int row = tid >> 1, sub = tid & 1;
+  const bool row_ok = row < nrows;
+  const float bound = row_ok ? sm.rbound[row] : 0.f;
+  int par = 0;
+
+  load_a(0);
+  load_b(0, 0);
+  for (int c0 = 0; c0 < h; c0 += kWC) {
+    const int ntile = min(4, (h - c0 + 31) >> 5);
+    floatx16 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+    for (int sl = 0; sl < nsl; ++sl) {
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const int f = tid + it * kThreads;
+        *(uint4*)(sm.u.st + (f >> 3) * kStride + (f & 7) * 16) = b_nxt[it];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a_cur[i] = a_nxt[i];
+      __syncthreads();
+      if (sl + 1 < nsl) {
+        load_a(sl + 1);
+        load_b(c0, sl + 1);
+      } else if (c0 + kWC < h) {
+        load_a(0);
+        load_b(c0 + kWC, 0);
+      }
+      slice_mfma<PREC>(ntile, acc, a_cur, sm.u.st, li, lh);
+    }
+
+    // ---- selection: 64 columns at a time ----
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int cb = c0 + 64 * half;
+      if (cb >= h) break;
+      __syncthreads();
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        const int t = 2 * half + tt;
+        const int c = cb + 32 * tt + li;
+        const float qc = c < h ? sm.qn[c] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+          sm.u.ck[i * kCK + 32 * tt + li] = qc - 2.f * acc[t][r];
+        }
+      }
+      __syncthreads();
+      uint64_t kk[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        const int c = cb + sub + 2 * j;
+        kk[j] = (row_ok && c < h) ? w_pack(sm.u.ck[row * kCK + sub + 2 * j], (uint32_t)c) : ~0ull;
+      }
+      const uint64_t* cur = &sm.lst[par][row * (KL + 1)];
+      uint64_t* nxt = &sm.lst[par ^ 1][row * (KL + 1)];
+      const int len = row_ok ? sm.rlen[row] : 0;
+      const float band = PREC == PREC_F32 ? 0.f : kBandBF16 * sqrtf(sm.rvn[row]) * sm.qmax;
+      int ptr = 0, w = 0;
+      float P = 0.f, K0 = 0.f;
+      bool cut = false;
+      uint64_t last = 0;
+      bool act = row_ok;
+      while (__any(act)) {
+        uint64_t best = ~0ull;
+        if (act) {
+#pragma unroll
+          for (int j = 0; j < 32; ++j)
+            if (kk[j] > last && kk[j] < best) best = kk[j];
+        }
+        const uint64_t o = w_shfl1(best);
+        best = o < best ? o : best;
+        if (act) {
+          const uint64_t lc = ptr < len ? cur[ptr] : ~0ull;
+          const uint64_t take = lc < best ? lc : best;
+          if (take == ~0ull) {
+            act = false;
+          } else if (cut && (PREC == PREC_F32 || w_unpack(take) > K0 + band)) {
+            act = false;
+          } else if (w >= KL) {
+            // the list is full: remember the smallest key left out; the
+            // final lists are certified against it after the exact re-sort
+            act = false;
+            if (sub == 0) sm.rdrop[row] = fminf(sm.rdrop[row], w_unpack(take));
+          } else {
+            if (lc < best) ++ptr;
+            else last = best;
+            if (sub == 0) nxt[w] = take;
+            ++w;
+            if (!cut) {
+              P += sm.cap[(uint32_t)take];
+              if (w >= kef || (kCapStop && P >= bound)) {
+                cut = true;
+                K0 = w_unpack(take);
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (sub == 0 && row_ok) {
+        sm.rlen[row] = w;
+        sm.rcut[row] = cut ? 1 : 0;
+      }
+      par ^= 1;
+    }
+  }
+  __syncthreads();
+
+  // ---------------- exact distances of the final lists ----------------
+  const int len = row_ok ? sm.rlen[row] : 0;
+  const uint64_t* L = &sm.lst[par][row * (KL + 1)];
+  if constexpr (PREC == PREC_F32) {
+    for (int l = sub; l < len; l += 2) {
+      const uint64_t e = L[l];
+      const int pos = (int)(uint32_t)e;
+      float d2 = sm.rvn[row] + w_unpack(e);
+      bool need = !(d2 >= kGuardW * (sm.rvn[row] + sm.qn[pos]));
+      if (MODE != P1_TABLE_FULL && a.method == LCEMD_OMR && l == 0) need = true;
+      if (need) d2 = w_exact_d2(a.V, a.m_pad, sm.rid[row], sm.cid[pos]);
+      sm.u.zb[row * (KL + 1) + l] = d2;
+    }
+  } else {
+    constexpr int KH = (KL + 1) / 2;
+    float ex[KH];
+    int ps[KH];
+#pragma unroll
+    for (int e = 0; e < KH; ++e) {
+      ex[e] = 0.f;
+      const int l = sub + 2 * e;
+      ps[e] = l < len ? (int)(uint32_t)L[l] : 0;
+    }
+    const float* vr = a.V + (size_t)sm.rid[row] * a.m_pad;
+    for (int d0 = 0; d0 < a.m_pad; d0 += kQD) {
+      __syncthreads();
+      for (int f = tid; f < h * 2; f += kThreads) {
+        const int c = f >> 1, q = f & 1;
+        *(float4*)(&sm.u.qs[c * kQS + q * 4]) = *(const float4*)(a.V + (size_t)sm.cid[c] * a.m_pad + d0 + q * 4);
+      }
+      __syncthreads();
+      if (row_ok) {
+        const float4 v0 = *(const float4*)(vr + d0), v1 = *(const float4*)(vr + d0 + 4);
+#pragma unroll
+        for (int e = 0; e < KH; ++e) {
+          if (sub + 2 * e < len) {
+            const float4* qp = (const float4*)(&sm.u.qs[ps[e] * kQS]);
+            const float4 q0 = qp[0], q1 = qp[1];
+            float s = ex[e];
+            float dd;
+            dd = v0.x - q0.x; s = fmaf(dd, dd, s); dd = v0.y - q0.y; s = fmaf(dd, dd, s);
+            dd = v0.z - q0.z; s = fmaf(dd, dd, s); dd = v0.w - q0.w; s = fmaf(dd, dd, s);
+            dd = v1.x - q1.x; s = fmaf(dd, dd, s); dd = v1.y - q1.y; s = fmaf(dd, dd, s);
+            dd = v1.z - q1.z; s = fmaf(dd, dd, s); dd = v1.w - q1.w; s = fmaf(dd, dd, s);
+            ex[e] = s;
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < KH; ++e) {
+      const int l = sub + 2 * e;
+      if (l < len) sm.u.zb[row * (KL + 1) + l] = ex[e];
+    }
+  }
+  __syncthreads();
+
+  if (sub == 0 && row_ok) {
+    uint64_t* Lw = &sm.lst[par][row * (KL + 1)];
+    float* Z2 = &sm.u.zb[row * (KL + 1)];
+    if constexpr (PREC != PREC_F32) {
+      for (int i = 1; i < len; ++i) {
+        const uint64_t e = w_pack(Z2[i], (uint32_t)Lw[i]);
+        int j = i - 1;
+        while (j >= 0 && w_pack(Z2[j], (uint32_t)Lw[j]) > e) {
+          Lw[j + 1] = Lw[j];
+          Z2[j + 1] = Z2[j];
+          --j;
+        }
+        Lw[j + 1] = e;
+        Z2[j + 1] = w_unpack(e);
+      }
+    }
+    int D = 0;
+    bool covered = false;
+    {
+      float Pc = 0.f;
+      for (int l = 0; l < len; ++l) {
+        ++D;
+        Pc += sm.cap[(uint32_t)Lw[l]];
+        if (D >= kef) { covered = true; break; }
+        if (kCapStop) {
+          if (Pc >= bound) { covered = true; break; }
+          if (a.method == LCEMD_OMR && l == 0 && Z2[0] != 0.f) { covered = true; break; }
+        }
+      }
+    }
+    // the merge cut this list (k_eff or capacity reached in key order); a
+    // shortfall after the exact re-sort is a rounding residue of the
+    // capacity sum, which the last entry absorbs
+    if (!covered && sm.rcut[row]) covered = true;
+    if (!covered && D < h && a.overflow) a.overflow[0] = 1;
+    // a candidate left out of a full list has a key >= rdrop - half a band
+    // (bf16; exact keys for float32): the used entries must all be nearer
+    if (PREC != PREC_F32 && D > 0 && sm.rdrop[row] < INFINITY && a.overflow) {
+      const float half_band = PREC == PREC_F32 ? 0.f : 0.5f * kBandBF16 * sqrtf(sm.rvn[row]) * sm.qmax;
+      const float last_key = Z2[D - 1] - sm.rvn[row];
+      if (!(last_key < sm.rdrop[row] - half_band - 1e-6f * (sm.rvn[row] + sm.qmax * sm.qmax))) {
+        // redo this row exactly (k_fix_rows) unless the list of such rows is full
+        int slot = a.fix_cap;
+        if (MODE != P1_PAIR && a.fix_list) slot = atomicAdd(a.fix_count, 1);
+        if (slot < a.fix_cap) a.fix_list[slot] = out_row0 + row;
+        else a.overflow[0] = 1;
+      }
+    }
+    if constexpr (MODE == P1_TABLE) {
+      float2* out = a.ZW + (out_row0 + row) * (int64_t)a.KT;
+      for (int l = 0; l < D && l < a.KT; ++l) {
+        const int pos = (int)(uint32_t)Lw[l];
+        out[l] = make_float2(sqrtf(fmaxf(Z2[l], 0.f)), l == D - 1 ? INFINITY : sm.cap[pos]);
+      }
+      if (D > a.KT && a.overflow) a.overflow[0] = 1;
+    } else if constexpr (MODE == P1_TABLE_FULL) {
+      const int64_t o0 = (out_row0 + row) * (int64_t)a.k;
+      for (int l = 0; l < a.k; ++l) {
+        if (l < D) {
+          const int pos = (int)(uint32_t)Lw[l];
+          a.S[o0 + l] = pos;
+          a.Z[o0 + l] = sqrtf(fmaxf(Z2[l], 0.f));
+          a.W[o0 + l] = sm.cap[pos];
+        } else {
+          a.S[o0 + l] = -1;
+          a.Z[o0 + l] = 0.f;
+          a.W[o0 + l] = 0.f;
+        }
+      }
+    } else {
+      float rem = bound, cost = 0.f;
+      for (int l = 0; l < D; ++l) {
+        const float w = sm.cap[(uint32_t)Lw[l]];
+        const float r = l == D - 1 ? rem : fminf(rem, w);
+        rem -= r;
+        cost = fmaf(r, sqrtf(fmaxf(Z2[l], 0.f)), cost);
+      }
+      sm.rcost[row] = cost;
+    }
+  }
+  if constexpr (MODE == P1_PAIR) {
+    __syncthreads();
+    if (tid == 0) {
+      float tot = 0.f;
+      for (int r = 0; r < nrows; ++r) tot += sm.rcost[r];
+      a.partial[pidx * a.rb_max + rb] = tot;
+    }
+  }
+}
+
+template <int MODE, int KL, int PREC>
+static hipError_t launch_wide_one(const P1Args& a, hipStream_t s) {
+  const size_t shmem = sizeof(WideSmem<KL, PREC>);
+  hipError_t e = hipFuncSetAttribute((const void*)k_phase1_wide<MODE, KL, PREC>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  dim3 grid;
+  if (MODE == P1_PAIR) {
+    grid = dim3((unsigned)a.npairs, (unsigned)a.rb_max, 1);
+  } else {
+    const int64_t nrb = (a.v_used + kWR - 1) / kWR;
+    const int64_t total = (a.nq + kGroupW - 1) / kGroupW * nrb * kGroupW;
+    const int64_t blocks = (total + 7) / 8 * 8;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    grid = dim3((unsigned)blocks, 1, 1);
+  }
+  hipLaunchKernelGGL((k_phase1_wide<MODE, KL, PREC>), grid, dim3(kThreads), shmem, s, a);
+  return hipGetLastError();
+}
+
+template <int MODE, int PREC>
+static hipError_t launch_wide_mode(const P1Args& a, int KL, hipStream_t s) {
+  if (KL <= 2) return launch_wide_one<MODE, 2, PREC>(a, s);
+  if (KL <= 4) return launch_wide_one<MODE, 4, PREC>(a, s);
+  if (KL <= 8) return launch_wide_one<MODE, 8, PREC>(a, s);
+  if (KL <= 16) return launch_wide_one<MODE, 16, PREC>(a, s);
+  if (KL <= 32) return launch_wide_one<MODE, 32, PREC>(a, s);
+  return hipErrorInvalidValue;
+}
+
+template <int PREC>
+static hipError_t launch_wide_prec(const P1Args& a, int mode, int KL, hipStream_t s) {
+  switch (mode) {
+    case P1_TABLE: return launch_wide_mode<P1_TABLE, PREC>(a, KL, s);
+    case P1_TABLE_FULL: return launch_wide_mode<P1_TABLE_FULL, PREC>(a, KL, s);
+    case P1_PAIR: return launch_wide_mode<P1_PAIR, PREC>(a, KL, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Exact redo of single table rows (bf16 rows whose certificate failed):
+// float32 squared distances to all of the query's words by direct
+// differences, a full bitonic sort by (distance, position), then the same
+// cut and outputs as the table modes.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* __restrict__ list) {
+  __shared__ float vrow[4096];
+  __shared__ uint64_t keys[kSeg];
+  const int tid = threadIdx.x;
+  const int64_t flat = list[blockIdx.x];
+  const int64_t qi = flat / a.v_used, r = flat % a.v_used;
+  const int64_t b = a.q0 + qi;
+  const int64_t s0 = a.qptr[b];
+  const int h = (int)(a.qptr[b + 1] - s0);
+  const int vid = a.used[r];
+  for (int d = tid; d < a.m_pad; d += kThreads) vrow[d] = a.V[(size_t)vid * a.m_pad + d];
+  __syncthreads();
+  for (int c = tid; c < kSeg; c += kThreads) {
+    uint64_t kk = ~0ull;
+    if (c < h) {
+      const float4* q = (const float4*)(a.V + (size_t)a.qcol[s0 + c] * a.m_pad);
+      float d2 = 0.f;
+      for (int d = 0; d < (a.m_pad >> 2); ++d) {
+        const float4 y = q[d];
+        float e;
+        e = vrow[4 * d] - y.x; d2 = fmaf(e, e, d2);
+        e = vrow[4 * d + 1] - y.y; d2 = fmaf(e, e, d2);
+        e = vrow[4 * d + 2] - y.z; d2 = fmaf(e, e, d2);
+        e = vrow[4 * d + 3] - y.w; d2 = fmaf(e, e, d2);
+      }
+      kk = w_pack(d2, (uint32_t)c);
+    }
+    keys[c] = kk;
+  }
+  __syncthreads();
+  for (int k = 2; k <= kSeg; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < kSeg / 2; i += kThreads) {
+        const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+        const int hi = lo + j;
+        const bool asc = (lo & k) == 0;
+        const uint64_t x = keys[lo], y = keys[hi];
+        if ((x > y) == asc) {
+          keys[lo] = y;
+          keys[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid != 0) return;
+  int kef;
+  const float bound = MODE == P1_TABLE ? a.xmax[r] : INFINITY;
+  if (MODE == P1_TABLE_FULL) kef = min(a.k, h);
+  else if (a.method == LCEMD_ICT) kef = h;
+  else if (a.method == LCEMD_OMR) kef = min(2, h);
+  else if (a.method == LCEMD_RWMD) kef = 1;
+  else kef = min(a.k, h);
+  int D = 0;
+  float Pc = 0.f;
+  for (int l = 0; l < h; ++l) {
+    ++D;
+    Pc += a.qval[s0 + (uint32_t)keys[l]];
+    if (D >= kef) break;
+    if (MODE == P1_TABLE) {
+      if (Pc >= bound) break;
+      if (a.method == LCEMD_OMR && l == 0 && w_unpack(keys[0]) != 0.f) break;
+    }
+  }
+  if (MODE == P1_TABLE) {
+    if (D > a.KT) {
+      a.overflow[0] = 1;
+      return;
+    }
+    float2* out = a.ZW + flat * (int64_t)a.KT;
+    for (int l = 0; l < D; ++l) {
+      const int pos = (int)(uint32_t)keys[l];
+      out[l] = make_float2(sqrtf(fmaxf(w_unpack(keys[l]), 0.f)), l == D - 1 ? INFINITY : a.qval[s0 + pos]);
+    }
+  } else {
+    const int64_t o0 = flat * (int64_t)a.k;
+    for (int l = 0; l < a.k; ++l) {
+      if (l < D) {
+        const int pos = (int)(uint32_t)keys[l];
+        a.S[o0 + l] = pos;
+        a.Z[o0 + l] = sqrtf(fmaxf(w_unpack(keys[l]), 0.f));
+        a.W[o0 + l] = a.qval[s0 + pos];
+      } else {
+        a.S[o0 + l] = -1;
+        a.Z[o0 + l] = 0.f;
+        a.W[o0 + l] = 0.f;
+      }
+    }
+  }
+}
+
+hipError_t launch_fix_rows(const P1Args& a, int mode, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (a.m_pad > 4096) return hipErrorInvalidValue;
+  if (mode == P1_TABLE)
+    hipLaunchKernelGGL(k_fix_rows<P1_TABLE>, dim3((unsigned)count), dim3(kThreads), 0, s, a, a.fix_list);
+  else if (mode == P1_TABLE_FULL)
+    hipLaunchKernelGGL(k_fix_rows<P1_TABLE_FULL>, dim3((unsigned)count), dim3(kThreads), 0, s, a, a.fix_list);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+int phase1_wide_rows() { return kWR; }
+
+hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, hipStream_t s) {
+  if (prec == PREC_F32) return launch_wide_prec<PREC_F32>(a, mode, KL, s);
+  if (prec == PREC_BF16) {
+    if (!a.Vb) return hipErrorInvalidValue;
+    return launch_wide_prec<PREC_BF16>(a, mode, KL, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lcemd

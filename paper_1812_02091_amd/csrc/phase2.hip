@@ -29,15 +29,36 @@ __device__ __forceinline__ float wave_sum(float t) {
   return t;
 }
 
+// One transfer step of Eq. (6)-(8) against table entry (z, w).
+__device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
+  const float r = fminf(rem, w);
+  rem -= r;
+  acc = fmaf(r, z, acc);
+}
+
+// EVEN: the table stride is even, so every row starts 16-byte aligned and
+// the first two entries of all QB queries are fetched as independent
+// 16-byte loads before any of them is consumed (the walk along a row is a
+// chain of dependent loads otherwise).  Entries past a row's sink are read
+// but never used: the sink leaves no mass.
+template <bool EVEN>
 __global__ __launch_bounds__(kThreads) void k_phase2(const int64_t* __restrict__ xptr,
                                                      const int2* __restrict__ xcv, int64_t n,
                                                      const float2* __restrict__ ZW, int64_t v_used,
                                                      int KT, int64_t nq, float* __restrict__ out,
                                                      int64_t ld) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t q0 = (int64_t)blockIdx.y * kQB;
+  // XCD-aware order: workgroup i runs on XCD i % 8; each XCD walks a
+  // contiguous range of (query group, document chunk) tiles, documents
+  // fastest, so the hot rows of its queries' tables stay in its L2.
+  const int64_t nchunks = (n + kDocsPerWG - 1) / kDocsPerWG;
+  const int64_t total = (nq + kQB - 1) / kQB * nchunks;
+  const int64_t per = (int64_t)gridDim.x / 8;
+  const int64_t work = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (work >= total) return;
+  const int64_t q0 = (work / nchunks) * kQB;
   const int nqb = (int)min((int64_t)kQB, nq - q0);
-  const int64_t ubase = (int64_t)blockIdx.x * kDocsPerWG + wave * kDocsPerWave;
+  const int64_t ubase = (work % nchunks) * kDocsPerWG + wave * kDocsPerWave;
   for (int j = 0; j < kDocsPerWave; ++j) {
     const int64_t u = ubase + j;
     if (u >= n) break;
@@ -48,19 +69,44 @@ __global__ __launch_bounds__(kThreads) void k_phase2(const int64_t* __restrict__
     for (int64_t e = e0 + lane; e < e1; e += 64) {
       const int2 cv = xcv[e];
       const float x = __int_as_float(cv.y);
+      const float2* row[kQB];
 #pragma unroll
-      for (int q = 0; q < kQB; ++q) {
-        if (q < nqb) {
-          const float2* row = ZW + ((q0 + q) * v_used + cv.x) * (int64_t)KT;
-          float rem = x, acc = 0.f;
-          for (int l = 0; l < KT; ++l) {
-            const float2 zw = row[l];
-            const float r = fminf(rem, zw.y);
-            rem -= r;
-            acc = fmaf(r, zw.x, acc);
-            if (rem <= 0.f) break;
+      for (int q = 0; q < kQB; ++q) row[q] = ZW + ((q0 + min(q, nqb - 1)) * v_used + cv.x) * (int64_t)KT;
+      if constexpr (EVEN) {
+        float4 f[kQB];
+#pragma unroll
+        for (int q = 0; q < kQB; ++q) f[q] = *(const float4*)row[q];
+#pragma unroll
+        for (int q = 0; q < kQB; ++q) {
+          if (q < nqb) {
+            float rem = x, acc = 0.f;
+            step(rem, acc, f[q].x, f[q].y);
+            if (rem > 0.f) {
+              step(rem, acc, f[q].z, f[q].w);
+              for (int l = 2; rem > 0.f && l < KT; l += 2) {
+                const float4 g = *(const float4*)(row[q] + l);
+                step(rem, acc, g.x, g.y);
+                if (rem > 0.f) step(rem, acc, g.z, g.w);
+              }
+            }
+            t[q] += acc;
           }
-          t[q] += acc;
+        }
+      } else {
+        float2 f[kQB];
+#pragma unroll
+        for (int q = 0; q < kQB; ++q) f[q] = row[q][0];
+#pragma unroll
+        for (int q = 0; q < kQB; ++q) {
+          if (q < nqb) {
+            float rem = x, acc = 0.f;
+            step(rem, acc, f[q].x, f[q].y);
+            for (int l = 1; rem > 0.f && l < KT; ++l) {
+              const float2 g = row[q][l];
+              step(rem, acc, g.x, g.y);
+            }
+            t[q] += acc;
+          }
         }
       }
     }
@@ -76,9 +122,15 @@ hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const 
                          int64_t v_used, int KT, int64_t nq, float* out, int64_t ld,
                          hipStream_t s) {
   if (n <= 0 || nq <= 0) return hipSuccess;
-  dim3 grid((unsigned)((n + kDocsPerWG - 1) / kDocsPerWG), (unsigned)((nq + kQB - 1) / kQB));
-  hipLaunchKernelGGL(k_phase2, grid, dim3(kThreads), 0, s, xptr, xcv, n, ZW, v_used, KT, nq, out,
-                     ld);
+  const int64_t total = (nq + kQB - 1) / kQB * ((n + kDocsPerWG - 1) / kDocsPerWG);
+  const int64_t blocks = (total + 7) / 8 * 8;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (KT % 2 == 0)
+    hipLaunchKernelGGL(k_phase2<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, xptr, xcv, n,
+                       ZW, v_used, KT, nq, out, ld);
+  else
+    hipLaunchKernelGGL(k_phase2<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, xptr, xcv, n,
+                       ZW, v_used, KT, nq, out, ld);
   return hipGetLastError();
 }
 

@@ -75,6 +75,7 @@ _SIGS = {
                                C.c_void_p, C.c_void_p, C.c_void_p]),
     "lcemd_used_vocab": (C.c_int64, [C.c_void_p, C.c_void_p]),
     "lcemd_profile": (C.c_int, [C.c_void_p, C.c_int]),
+    "lcemd_counters": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "lcemd_profile_get": (C.c_int, [C.c_void_p, C.POINTER(lcemd_phase_time), C.c_int]),
     "lcemd_server_start": (C.c_int, [C.c_void_p, C.POINTER(lcemd_server_cfg),
                                      C.POINTER(C.c_void_p)]),
@@ -290,6 +291,13 @@ class Context:
         self.lib.lcemd_profile_get(self.h, arr, cnt)
         return [dict(name=arr[i].name.decode(), ms=arr[i].ms, launches=arr[i].launches,
                      work=arr[i].work) for i in range(cnt)]
+
+    def counters(self):
+        """(query tiles redone with float32 keys / deeper lists, bf16 rows
+        redone exactly one by one), cumulative since creation."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(self.lib.lcemd_counters(self.h, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
 
     @property
     def n(self) -> int:

@@ -295,3 +295,23 @@ def test_topl_bf16_text(text_small):
     o = _oracle_matrix(orc, w, "act", 8, "sym")
     for b in range(w.queries.n):
         P.check_topl(idx[b], dist[b], o[b], 16, f"b={b}")
+
+
+@pytest.mark.parametrize("force", ["1", "2"])
+def test_other_phase1_kernels(L, force, monkeypatch):
+    """The 64-row streaming kernel (force=1) and the whole-row kernel
+    (force=2) give the same results as the default kernel choice."""
+    monkeypatch.setenv("LCEMD_FORCE_KERNEL", force)
+    w = make_workload("text", n=90, B=3, v=3000)
+    ctx = _ctx(L, w)
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    say(f"[gpu] phase-1 kernel variant {force}")
+    for method, k in (("act", 3), ("ict", 1), ("omr", 1), ("rwmd", 1)):
+        g = ctx.distances(*_q(w), method=method, k=k, direction="sym")
+        o = _oracle_matrix(orc, w, method, k, "sym")
+        P.assert_distances(g, o, f"variant {force} {method}{k}")
+    S, Z, W = ctx.tables(*_q(w), k=4)
+    for b in range(w.queries.n):
+        qc, qw = w.queries.row(b)
+        So, Zo, Wo, R = orc.tables(qc, qw, 4)
+        P.check_table_rows(S[b], Z[b], W[b], So, R, qw, 4, qc.size)
