@@ -213,36 +213,58 @@ int lcemd_profile_get(lcemd_ctx* ctx, lcemd_phase_time* out, int cap);
 
 /* ---------------------------------------------------------------------
  * Serving: continuous batching of a query stream against the resident
- * database.  Submitted queries wait in an admission queue; a worker thread
- * admits them into free slots while their device memory fits the budget,
- * runs their phase 1 as one batch and their phase 2 on a persistent kernel
- * fed by a device work queue, and completes each query independently.
- * Results do not depend on which other queries shared the device.
+ * database, returning each query's symmetric top-l (Sec. 5, Eq. 10 with the
+ * exact pruning of lcemd_topl).  Submitted queries wait in a FIFO; a worker
+ * thread admits them into a free lane (a stream with preallocated device
+ * and pinned host buffers for up to B queries and W words), runs the lane's
+ * whole batch -- phase 1 tables, the exact redo of uncertified bfloat16
+ * rows, phase 2 on a persistent kernel fed by per-XCD work counters, D2Q
+ * candidate selection, Q2D of the candidates, symmetric top-l -- and
+ * completes each query independently.  A query whose top-l certificate
+ * fails, or whose lists overflowed, is finished by lcemd_topl.
+ *
+ * Results depend only on the query, never on the others sharing a batch.
+ * For RWMD, OMR and ACT (k <= the query's word count) they are also the
+ * bits lcemd_topl gives for the query alone; ICT serves with 64-entry
+ * tables on every query, so its results can differ from lcemd_topl's
+ * (whose first-try depth follows the batch) by float32 rounding.
+ *
+ * While a server runs, its worker thread owns the context: make no other
+ * call on that context until lcemd_server_stop returns.
  * --------------------------------------------------------------------- */
 typedef struct lcemd_server lcemd_server;
 
 typedef struct {
-  int32_t method;        /* as lcemd_opts */
-  int32_t k;
-  int32_t precision;
-  int32_t l;             /* neighbours returned per query */
-  int32_t max_slots;     /* queries in flight at once (>= 1) */
-  int32_t max_batch_words; /* words admitted into one phase-1 batch */
-  int64_t memory_budget; /* device bytes for in-flight query state */
-  int32_t use_graph;     /* capture the per-batch launches in a hipGraph */
-  int32_t reserved[5];
+  int32_t method;          /* as lcemd_opts */
+  int32_t k;               /* ACT only, 1..LCEMD_MAX_K */
+  int32_t precision;       /* LCEMD_FP32 or LCEMD_BF16 */
+  int32_t l;               /* neighbours returned per query, 1..min(LCEMD_MAX_L, n) */
+  int32_t max_slots;       /* queries per batch (>= 1); lowered to fit memory_budget */
+  int32_t max_batch_words; /* words per batch; values below LCEMD_MAX_HIST mean LCEMD_MAX_HIST */
+  int64_t memory_budget;   /* device bytes for all lanes' buffers; 0 = 4 GiB */
+  int32_t use_graph;       /* nonzero: two lanes, each batch replayed as a captured hipGraph;
+                              zero: one lane, kernels launched per batch */
+  int32_t reserved[5];     /* must be 0 */
 } lcemd_server_cfg;
 
+/* Allocates every lane buffer up front.  LCEMD_E_CAPACITY if the budget
+ * holds no query; LCEMD_E_UNSUPPORTED for LCEMD_FP8.  *out is NULL on
+ * error. */
 int lcemd_server_start(lcemd_ctx* ctx, const lcemd_server_cfg* cfg, lcemd_server** out);
-/* Queue one query (host arrays, h words, canonical form).  *ticket gets
- * its id.  LCEMD_E_CAPACITY if the query can never fit the budget. */
+/* Queue one query (host arrays of h words: ascending distinct ids < v,
+ * weights >= 0 summing to 1; copied before return).  *ticket gets its id.
+ * LCEMD_E_BAD_CSR for a malformed query, LCEMD_E_CAPACITY for h >
+ * LCEMD_MAX_HIST.  Thread-safe. */
 int lcemd_server_submit(lcemd_server* s, const int32_t* col, const float* val, int32_t h,
                         uint64_t* ticket);
-/* Block until `ticket` completes; writes l (idx, dist) pairs and the
- * seconds from submit to completion. */
+/* Block until `ticket` completes; writes l (idx, dist) pairs in ascending
+ * distance and the seconds from submit to completion (any output pointer
+ * may be NULL).  Each ticket is waited for once; unknown or already waited
+ * tickets give LCEMD_E_INVALID_ARG.  Thread-safe. */
 int lcemd_server_wait(lcemd_server* s, uint64_t ticket, int64_t* idx, float* dist,
                       double* latency_s);
-/* Drain and stop; frees the server.  NULL-safe. */
+/* Finish every queued query, stop the worker and free the server (results
+ * not yet waited for are dropped).  NULL-safe. */
 void lcemd_server_stop(lcemd_server* s);
 
 #ifdef __cplusplus

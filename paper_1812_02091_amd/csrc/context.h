@@ -1,0 +1,115 @@
+// Host-side context of the lcemd library and the helpers shared by the
+// C-ABI entry points (api.cpp) and the serving engine (server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+  double work;
+};
+
+struct lcemd_ctx {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // embeddings (Sec. 4: V)
+  int64_t v = 0;
+  int m = 0, m_pad = 0;
+  float* V = nullptr;
+  float* vnorm = nullptr;
+  uint16_t* Vb = nullptr;
+  // database (Sec. 4: X in CSR)
+  int64_t n = 0, nnz = 0, v_used = 0;
+  int db_hmax = 0;
+  int64_t* xptr = nullptr;
+  int2* xcv = nullptr;
+  int32_t* xcol = nullptr;
+  int32_t* used = nullptr;
+  float* xmax = nullptr;
+  std::vector<int32_t> used_host;
+  // scratch, grow-only
+  std::map<std::string, DevBuf> ws;
+  size_t table_budget = size_t(12) << 30;
+  int force_kernel = 0;   // test hook (LCEMD_FORCE_KERNEL): 1 = skip the 128-row kernel, 2 = deep kernel
+  int64_t fallbacks = 0;  // tiles redone with float32 keys / deeper lists
+  int64_t fixed_rows = 0; // bf16 table rows redone exactly one by one
+  // profiling
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<lcemd_phase_time> last;
+};
+
+namespace lcemd_host {
+
+int fail(lcemd_ctx* c, int code, const char* fmt, ...);
+int check_csr_host(lcemd_ctx* c, const char* what, const int64_t* ptr, const int32_t* col,
+                   const float* val, int64_t rows, int64_t v, bool require_norm, int* hmax);
+int ensure_precision(lcemd_ctx* c, int prec);
+int p1_launch(lcemd_ctx* c, lcemd::P1Args& a, int mode, int prec, int depth, int seg_hmax,
+              int row_hmax);
+int pow2ceil(int x);
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, LCEMD_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+inline void dfree(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+template <typename T>
+int dalloc(lcemd_ctx* c, T*& p, size_t count, const char* what) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, LCEMD_E_OOM, "device allocation of %zu bytes for %s failed",
+                count * sizeof(T), what);
+  }
+  p = static_cast<T*>(q);
+  return LCEMD_OK;
+}
+
+// grow-only named scratch buffer
+template <typename T>
+int wsget(lcemd_ctx* c, const char* name, size_t count, T*& out) {
+  DevBuf& b = c->ws[name];
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (b.bytes < bytes) {
+    if (b.p) {
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, LCEMD_E_OOM, "scratch allocation of %zu bytes (%s) failed", bytes, name);
+    }
+    b.bytes = bytes;
+  }
+  out = static_cast<T*>(b.p);
+  return LCEMD_OK;
+}
+
+
+}  // namespace lcemd_host

@@ -110,5 +110,10 @@ hipError_t launch_unpack_topl(const uint64_t* cand, int64_t cand_ld, int64_t row
                               const int32_t* row_list, int L, int64_t* idx, float* dist,
                               hipStream_t s);
 hipError_t launch_max_inplace(float* a, const float* b, int64_t count, hipStream_t s);
+hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
+hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n,
+                                    const float2* ZW, int64_t v_used, int KT, const int* nq_dev,
+                                    float* out, int64_t ld, int* counters, int blocks,
+                                    hipStream_t s);
 
 }  // namespace lcemd

@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
     }
     const int64_t s0 = a.qptr[b];
     h = (int)(a.qptr[b + 1] - s0);
+    if (h <= 0) return;  // padding slot of a fixed-size batch
     for (int c = tid; c < h; c += kThreads) {
       const int w = a.qcol[s0 + c];
       sm.cid[c] = w;

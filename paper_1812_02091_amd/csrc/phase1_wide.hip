@@ -239,6 +239,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a) {
     }
     const int64_t s0 = a.qptr[b];
     h = (int)(a.qptr[b + 1] - s0);
+    if (h <= 0) return;  // padding slot of a fixed-size batch
     for (int c = tid; c < h; c += kThreads) {
       const int w = a.qcol[s0 + c];
       sm.cid[c] = w;
@@ -599,10 +600,12 @@ static hipError_t launch_wide_prec(const P1Args& a, int mode, int KL, hipStream_
 // cut and outputs as the table modes.
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* __restrict__ list) {
+  const int count = min(*a.fix_count, a.fix_cap);
+  for (int item = blockIdx.x; item < count; item += gridDim.x) {
   __shared__ float vrow[4096];
   __shared__ uint64_t keys[kSeg];
   const int tid = threadIdx.x;
-  const int64_t flat = list[blockIdx.x];
+  const int64_t flat = list[item];
   const int64_t qi = flat / a.v_used, r = flat % a.v_used;
   const int64_t b = a.q0 + qi;
   const int64_t s0 = a.qptr[b];
@@ -643,7 +646,7 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
       __syncthreads();
     }
   }
-  if (tid != 0) return;
+  if (tid == 0) {
   int kef;
   const float bound = MODE == P1_TABLE ? a.xmax[r] : INFINITY;
   if (MODE == P1_TABLE_FULL) kef = min(a.k, h);
@@ -665,12 +668,12 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
   if (MODE == P1_TABLE) {
     if (D > a.KT) {
       a.overflow[0] = 1;
-      return;
-    }
-    float2* out = a.ZW + flat * (int64_t)a.KT;
-    for (int l = 0; l < D; ++l) {
-      const int pos = (int)(uint32_t)keys[l];
-      out[l] = make_float2(sqrtf(fmaxf(w_unpack(keys[l]), 0.f)), l == D - 1 ? INFINITY : a.qval[s0 + pos]);
+    } else {
+      float2* out = a.ZW + flat * (int64_t)a.KT;
+      for (int l = 0; l < D; ++l) {
+        const int pos = (int)(uint32_t)keys[l];
+        out[l] = make_float2(sqrtf(fmaxf(w_unpack(keys[l]), 0.f)), l == D - 1 ? INFINITY : a.qval[s0 + pos]);
+      }
     }
   } else {
     const int64_t o0 = flat * (int64_t)a.k;
@@ -687,9 +690,13 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
       }
     }
   }
+  }
+  __syncthreads();
+  }
 }
 
 hipError_t launch_fix_rows(const P1Args& a, int mode, int count, hipStream_t s) {
+  // `count` bounds the grid; the kernel reads the live count from a.fix_count
   if (count <= 0) return hipSuccess;
   if (a.m_pad > 4096) return hipErrorInvalidValue;
   if (mode == P1_TABLE)

@@ -3,7 +3,7 @@
 // table row for word i, summed per database row (document).
 //
 // Each table row holds (z, w) pairs in ascending distance order; its last
-// valid entry carries w = +inf, so the loop below is Eq. (6)-(8) followed by
+// valid entry carries w = +inf, so the walk below is Eq. (6)-(8) followed by
 // Eq. (9) (the rest of the mass at the last distance) and always ends.
 //
 // Layout and mapping: a wave owns one database row at a time; its lanes
@@ -36,11 +36,73 @@ __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
   acc = fmaf(r, z, acc);
 }
 
+// Costs of database row u against queries q0 .. q0+nqb-1 (one wave).
 // EVEN: the table stride is even, so every row starts 16-byte aligned and
 // the first two entries of all QB queries are fetched as independent
 // 16-byte loads before any of them is consumed (the walk along a row is a
 // chain of dependent loads otherwise).  Entries past a row's sink are read
 // but never used: the sink leaves no mass.
+template <bool EVEN>
+__device__ __forceinline__ void doc_costs(int lane, int64_t u, int64_t q0, int nqb,
+                                          const int64_t* __restrict__ xptr,
+                                          const int2* __restrict__ xcv,
+                                          const float2* __restrict__ ZW, int64_t v_used, int KT,
+                                          float* __restrict__ out, int64_t ld) {
+  const int64_t e0 = xptr[u], e1 = xptr[u + 1];
+  float t[kQB];
+#pragma unroll
+  for (int q = 0; q < kQB; ++q) t[q] = 0.f;
+  for (int64_t e = e0 + lane; e < e1; e += 64) {
+    const int2 cv = xcv[e];
+    const float x = __int_as_float(cv.y);
+    const float2* row[kQB];
+#pragma unroll
+    for (int q = 0; q < kQB; ++q) row[q] = ZW + ((q0 + min(q, nqb - 1)) * v_used + cv.x) * (int64_t)KT;
+    if constexpr (EVEN) {
+      float4 f[kQB];
+#pragma unroll
+      for (int q = 0; q < kQB; ++q) f[q] = *(const float4*)row[q];
+#pragma unroll
+      for (int q = 0; q < kQB; ++q) {
+        if (q < nqb) {
+          float rem = x, acc = 0.f;
+          step(rem, acc, f[q].x, f[q].y);
+          if (rem > 0.f) {
+            step(rem, acc, f[q].z, f[q].w);
+            for (int l = 2; rem > 0.f && l < KT; l += 2) {
+              const float4 g = *(const float4*)(row[q] + l);
+              step(rem, acc, g.x, g.y);
+              if (rem > 0.f) step(rem, acc, g.z, g.w);
+            }
+          }
+          t[q] += acc;
+        }
+      }
+    } else {
+      float2 f[kQB];
+#pragma unroll
+      for (int q = 0; q < kQB; ++q) f[q] = row[q][0];
+#pragma unroll
+      for (int q = 0; q < kQB; ++q) {
+        if (q < nqb) {
+          float rem = x, acc = 0.f;
+          step(rem, acc, f[q].x, f[q].y);
+          for (int l = 1; rem > 0.f && l < KT; ++l) {
+            const float2 g = row[q][l];
+            step(rem, acc, g.x, g.y);
+          }
+          t[q] += acc;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kQB; ++q) {
+    const float s = wave_sum(t[q]);
+    if (lane == 0 && q < nqb) out[(q0 + q) * ld + u] = s;
+  }
+}
+
 template <bool EVEN>
 __global__ __launch_bounds__(kThreads) void k_phase2(const int64_t* __restrict__ xptr,
                                                      const int2* __restrict__ xcv, int64_t n,
@@ -62,59 +124,7 @@ __global__ __launch_bounds__(kThreads) void k_phase2(const int64_t* __restrict__
   for (int j = 0; j < kDocsPerWave; ++j) {
     const int64_t u = ubase + j;
     if (u >= n) break;
-    const int64_t e0 = xptr[u], e1 = xptr[u + 1];
-    float t[kQB];
-#pragma unroll
-    for (int q = 0; q < kQB; ++q) t[q] = 0.f;
-    for (int64_t e = e0 + lane; e < e1; e += 64) {
-      const int2 cv = xcv[e];
-      const float x = __int_as_float(cv.y);
-      const float2* row[kQB];
-#pragma unroll
-      for (int q = 0; q < kQB; ++q) row[q] = ZW + ((q0 + min(q, nqb - 1)) * v_used + cv.x) * (int64_t)KT;
-      if constexpr (EVEN) {
-        float4 f[kQB];
-#pragma unroll
-        for (int q = 0; q < kQB; ++q) f[q] = *(const float4*)row[q];
-#pragma unroll
-        for (int q = 0; q < kQB; ++q) {
-          if (q < nqb) {
-            float rem = x, acc = 0.f;
-            step(rem, acc, f[q].x, f[q].y);
-            if (rem > 0.f) {
-              step(rem, acc, f[q].z, f[q].w);
-              for (int l = 2; rem > 0.f && l < KT; l += 2) {
-                const float4 g = *(const float4*)(row[q] + l);
-                step(rem, acc, g.x, g.y);
-                if (rem > 0.f) step(rem, acc, g.z, g.w);
-              }
-            }
-            t[q] += acc;
-          }
-        }
-      } else {
-        float2 f[kQB];
-#pragma unroll
-        for (int q = 0; q < kQB; ++q) f[q] = row[q][0];
-#pragma unroll
-        for (int q = 0; q < kQB; ++q) {
-          if (q < nqb) {
-            float rem = x, acc = 0.f;
-            step(rem, acc, f[q].x, f[q].y);
-            for (int l = 1; rem > 0.f && l < KT; ++l) {
-              const float2 g = row[q][l];
-              step(rem, acc, g.x, g.y);
-            }
-            t[q] += acc;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kQB; ++q) {
-      const float s = wave_sum(t[q]);
-      if (lane == 0 && q < nqb) out[(q0 + q) * ld + u] = s;
-    }
+    doc_costs<EVEN>(lane, u, q0, nqb, xptr, xcv, ZW, v_used, KT, out, ld);
   }
 }
 
@@ -131,6 +141,63 @@ hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const 
   else
     hipLaunchKernelGGL(k_phase2<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, xptr, xcv, n,
                        ZW, v_used, KT, nq, out, ld);
+  return hipGetLastError();
+}
+
+// Persistent variant for fixed-shape (graph-captured) batches: a fixed grid
+// whose waves pull (query group, 4 database rows) items from eight work
+// counters, one per XCD, each counter walking a contiguous eighth of the
+// items.  The live query count is read from device memory; every wave exits
+// once its counter passes the end of its range.
+template <bool EVEN>
+__global__ __launch_bounds__(kThreads) void k_phase2_persistent(
+    const int64_t* __restrict__ xptr, const int2* __restrict__ xcv, int64_t n,
+    const float2* __restrict__ ZW, int64_t v_used, int KT, const int* __restrict__ nq_dev,
+    float* __restrict__ out, int64_t ld, int* __restrict__ counters) {
+  const int lane = threadIdx.x & 63;
+  const int xcd = blockIdx.x & 7;
+  const int64_t nq = *nq_dev;
+  const int64_t nd4 = (n + 3) / 4;
+  const int64_t total = (nq + kQB - 1) / kQB * nd4;
+  const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
+  while (true) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(&counters[xcd], 1);
+    const int64_t item = lo + __shfl(it, 0);
+    if (item >= hi) break;
+    const int64_t q0 = (item / nd4) * kQB;
+    const int nqb = (int)min((int64_t)kQB, nq - q0);
+    const int64_t ubase = (item % nd4) * 4;
+    for (int j = 0; j < 4; ++j) {
+      const int64_t u = ubase + j;
+      if (u >= n) break;
+      doc_costs<EVEN>(lane, u, q0, nqb, xptr, xcv, ZW, v_used, KT, out, ld);
+    }
+  }
+}
+
+__global__ void k_zero_ints(int* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_ints, dim3((count + 63) / 64), dim3(64), 0, s, p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n,
+                                    const float2* ZW, int64_t v_used, int KT, const int* nq_dev,
+                                    float* out, int64_t ld, int* counters, int blocks,
+                                    hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  blocks = (blocks + 7) / 8 * 8;
+  if (KT % 2 == 0)
+    hipLaunchKernelGGL(k_phase2_persistent<true>, dim3(blocks), dim3(kThreads), 0, s, xptr, xcv, n,
+                       ZW, v_used, KT, nq_dev, out, ld, counters);
+  else
+    hipLaunchKernelGGL(k_phase2_persistent<false>, dim3(blocks), dim3(kThreads), 0, s, xptr, xcv, n,
+                       ZW, v_used, KT, nq_dev, out, ld, counters);
   return hipGetLastError();
 }
 

@@ -308,6 +308,62 @@ class Context:
         self._n = value
 
 
+class Server:
+    """Continuous-batching server on a loaded Context (lcemd_server_*).  While
+    it runs, the context belongs to the server's worker thread."""
+
+    def __init__(self, ctx: "Context", method="act", k=8, precision="fp32", l=16,
+                 max_slots=64, max_batch_words=0, memory_budget=0, use_graph=True):
+        self.lib = ctx.lib
+        cfg = lcemd_server_cfg()
+        cfg.method = METHOD[method] if isinstance(method, str) else int(method)
+        cfg.k = int(k)
+        cfg.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        cfg.l = int(l)
+        cfg.max_slots = int(max_slots)
+        cfg.max_batch_words = int(max_batch_words)
+        cfg.memory_budget = int(memory_budget)
+        cfg.use_graph = int(bool(use_graph))
+        h = C.c_void_p()
+        rc = self.lib.lcemd_server_start(ctx.h, C.byref(cfg), C.byref(h))
+        if rc != OK:
+            raise LcemdError(rc, self.lib.lcemd_last_error(ctx.h).decode())
+        self.h = h
+        self.l = int(l)
+        self.ctx = ctx
+
+    def submit(self, col, val) -> int:
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float32)
+        t = C.c_uint64()
+        rc = self.lib.lcemd_server_submit(self.h, C.c_void_p(c.ctypes.data), C.c_void_p(v.ctypes.data),
+                                          int(c.shape[0]), C.byref(t))
+        if rc != OK:
+            raise LcemdError(rc, "submit rejected")
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        idx = np.empty(self.l, dtype=np.int64)
+        dist = np.empty(self.l, dtype=np.float32)
+        lat = C.c_double()
+        rc = self.lib.lcemd_server_wait(self.h, C.c_uint64(ticket), C.c_void_p(idx.ctypes.data),
+                                        C.c_void_p(dist.ctypes.data), C.byref(lat))
+        if rc != OK:
+            raise LcemdError(rc, "query failed")
+        return idx, dist, float(lat.value)
+
+    def stop(self):
+        if getattr(self, "h", None):
+            self.lib.lcemd_server_stop(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+
 def check_histograms(rowptr, col, val, v: int, require_normalized: bool = True):
     """Host-side validation of a CSR histogram batch (no GPU needed): returns
     (status code, message)."""
