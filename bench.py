@@ -43,6 +43,12 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=2, help="queries in the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the bf16-path comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="offered load, queries/s")
+    ap.add_argument("--serve-queries", type=int, default=1000)
+    ap.add_argument("--serve-sat", type=int, default=256, help="queries in the saturation sample")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-budget", type=int, default=8, help="GiB of device memory for lanes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scales FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -97,6 +103,82 @@ def cpu_baseline(w, method, k, ell, nq):
     return {"value": pairs / dt, "unit": "distances/s", "cores": cores, "kind": "oracle",
             "sample": f"{nq} queries x all {w.db.n} database rows, {method.upper()} k={k} symmetric "
                       f"+ top-{ell}, float64 numpy/scipy, {cores} worker processes, {dt:.1f} s of oracle time per worker"}
+
+
+def serving_bench(a, lcemd):
+    """Serving on the 1M-word / 1M-document workload: a Poisson query stream
+    (open loop; 10-500 words per query) against the resident database, ACT
+    k=8, symmetric top-16.  Two paths: bf16 phase 1 on two graph-captured
+    lanes with continuous admission, and float32 phase 1 on one lane with
+    kernels launched per batch and a batch admitted only when the previous
+    one is done.  Latency = completion - scheduled arrival."""
+    import threading
+
+    import numpy as np
+
+    from synth import arrival_trace, make_workload
+
+    t0 = time.time()
+    w = make_workload("text-1M", B=1)
+    print(f"[bench] serving workload built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
+    v = w.V.shape[0]
+    n = w.db.n
+    del w
+    _, qs = arrival_trace(a.serve_rate, a.serve_queries + a.serve_sat, v, lmin=10, lmax=500)
+    rows = [qs.row(b) for b in range(qs.n)]
+    res = {}
+    for prec, graph in (("bf16", True), ("fp32", False)):
+        srv = lcemd.Server(ctx, method="act", k=8, precision=prec, l=16, max_slots=a.serve_slots,
+                           memory_budget=a.serve_budget << 30, use_graph=graph)
+        for b in range(4):  # warm-up
+            srv.wait(srv.submit(*rows[b]))
+        # saturation throughput: the whole sample submitted at once
+        sat = rows[a.serve_queries:]
+        t1 = time.perf_counter()
+        tk = [srv.submit(c, x) for c, x in sat]
+        for t in tk:
+            srv.wait(t)
+        sat_qps = len(sat) / (time.perf_counter() - t1)
+        # open loop at the stated rate
+        rate = a.serve_rate
+        arr = np.cumsum(np.random.default_rng(55).exponential(1.0 / rate, a.serve_queries))
+        lag = np.zeros(a.serve_queries)
+        tickets = [0] * a.serve_queries
+        start = time.perf_counter() + 0.05
+
+        def feed():
+            for i in range(a.serve_queries):
+                d = start + arr[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                lag[i] = time.perf_counter() - (start + arr[i])
+                tickets[i] = srv.submit(*rows[i])
+
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        lat = np.empty(a.serve_queries)
+        for i in range(a.serve_queries):
+            lat[i] = srv.wait(tickets[i])[2] + lag[i]
+        span = time.perf_counter() - start
+        srv.stop()
+        res[prec] = {"path": ("bf16 keys, 2 graph-captured lanes, continuous admission" if graph else
+                              "float32 keys, 1 lane, per-batch launches, static FIFO batches"),
+                     "offered_qps": rate, "queries": a.serve_queries,
+                     "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                     "achieved_qps": a.serve_queries / span,
+                     "saturation_qps": sat_qps,
+                     "saturation_distances_per_s": sat_qps * n}
+        print(f"[bench] serving {prec}: {res[prec]}", file=sys.stderr, flush=True)
+    fb, fixed = ctx.counters()
+    ctx.close()
+    res["workload"] = (f"text-1M: vocab {v} x 300, {n} database histograms resident; Poisson arrivals, "
+                       f"10-500 words per query, ACT k=8 symmetric top-16, up to {a.serve_slots} "
+                       f"queries per batch; saturation = {a.serve_sat} queries submitted at once")
+    res["bf16_rows_redone_exactly"] = fixed
+    return res
 
 
 def main():
@@ -196,12 +278,15 @@ def main():
                    f"top{a.ell}_agreement_vs_{a.precision}": agree,
                    "max_rel_diff_of_returned_distances": maxrel}
 
+    ctx.close()
+    serving = None if a.no_serving else serving_bench(a, lcemd)
+
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(w, a.method, a.k, a.ell, min(a.cpu_queries, B))
 
     out = {
-        "metric": "query-doc ACT distances/sec",
+        "metric": "query-doc ACT distances/sec + p50/p99 query latency, BF16 vs FP32 path",
         "value": value,
         "unit": "distances/s",
         "n_gpus": 1,
@@ -222,6 +307,7 @@ def main():
         "cpu_baseline": cpu,
         "phases": phase_report,
         "other_precision": compare,
+        "serving": serving,
     }
     print(json.dumps(out))
 

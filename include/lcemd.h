@@ -240,7 +240,7 @@ typedef struct {
   int32_t precision;       /* LCEMD_FP32 or LCEMD_BF16 */
   int32_t l;               /* neighbours returned per query, 1..min(LCEMD_MAX_L, n) */
   int32_t max_slots;       /* queries per batch (>= 1); lowered to fit memory_budget */
-  int32_t max_batch_words; /* words per batch; values below LCEMD_MAX_HIST mean LCEMD_MAX_HIST */
+  int32_t max_batch_words; /* words per batch (raised to LCEMD_MAX_HIST); 0 = no limit */
   int64_t memory_budget;   /* device bytes for all lanes' buffers; 0 = 4 GiB */
   int32_t use_graph;       /* nonzero: two lanes, each batch replayed as a captured hipGraph;
                               zero: one lane, kernels launched per batch */

@@ -382,6 +382,17 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
   return LCEMD_OK;
 }
 
+// The L smallest keys of each row (scratch for the per-part first pass).
+int select_rows(lcemd_ctx* c, const float* keys, int64_t ld, int64_t n, int64_t rows, int L,
+                const int32_t* row_list, int64_t excl, uint64_t* out) {
+  uint64_t* tmp = nullptr;
+  const int64_t t = select_tmp_elems(rows, n, L);
+  int rc;
+  if (t > 0 && (rc = wsget(c, "select_tmp", (size_t)t, tmp))) return rc;
+  HIPCHK(c, launch_select(keys, ld, n, rows, L, row_list, excl, out, tmp, c->stream));
+  return LCEMD_OK;
+}
+
 // Q2D for an explicit list of pairs or candidates (see P1Args).
 int run_pairs(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, P1Args a, float* out,
               int64_t out_ld, int64_t per_row) {
@@ -732,7 +743,7 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
     uint64_t* cand;
     if ((rc = wsget(c, "cand", (size_t)B * l, cand))) return rc;
     if ((rc = prof_begin(c, "select", (double)B * n))) return rc;
-    HIPCHK(c, launch_select(d2q, n, n, B, l, nullptr, excl, cand, c->stream));
+    if ((rc = select_rows(c, d2q, n, n, B, l, nullptr, excl, cand))) return rc;
     if ((rc = prof_end(c))) return rc;
     HIPCHK(c, launch_unpack_topl(cand, l, B, nullptr, l, didx, ddist, c->stream));
   } else {
@@ -764,7 +775,7 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
         HIPCHK(c, hipMemcpyAsync(drows, rows.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream));
         uint64_t* cand;
         if ((rc = wsget(c, "cand", (size_t)R * l, cand))) return rc;
-        HIPCHK(c, launch_select(d2q, n, n, R, l, drows, excl, cand, c->stream));
+        if ((rc = select_rows(c, d2q, n, n, R, l, drows, excl, cand))) return rc;
         HIPCHK(c, launch_unpack_topl(cand, l, R, drows, l, didx, ddist, c->stream));
         break;
       }
@@ -773,7 +784,7 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
       float* q2v;
       if ((rc = wsget(c, "cand", (size_t)R * cld, cand)) || (rc = wsget(c, "cand_q2d", (size_t)R * use, q2v))) return rc;
       if ((rc = prof_begin(c, "select", (double)R * n))) return rc;
-      HIPCHK(c, launch_select(d2q, n, n, R, (int)cld, drows, excl, cand, c->stream));
+      if ((rc = select_rows(c, d2q, n, n, R, (int)cld, drows, excl, cand))) return rc;
       if ((rc = prof_end(c))) return rc;
       P1Args a = base_args(c, Q, o);
       a.cand = cand;

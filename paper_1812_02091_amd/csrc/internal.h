@@ -99,9 +99,14 @@ hipError_t launch_make_fp8(const float* V, int64_t v, int m_pad, uint8_t* out, f
 hipError_t launch_validate_csr(const int64_t* ptr, const int32_t* col, const float* val,
                                int64_t rows, int64_t v, int normalized, int* err,
                                hipStream_t s);
+// L smallest (distance, index) keys of each row; rows longer than one
+// workgroup's part go through a first pass per part into `tmp`
+// (select_tmp_elems entries; may be null when that is 0).
+int64_t select_parts(int64_t n);
+int64_t select_tmp_elems(int64_t rows, int64_t n, int L);
 hipError_t launch_select(const float* keys, int64_t ld, int64_t n, int64_t rows, int L,
                          const int32_t* row_list, int64_t exclude_base, uint64_t* out,
-                         hipStream_t s);
+                         uint64_t* tmp, hipStream_t s);
 hipError_t launch_finalize_sym(const uint64_t* cand, int64_t cand_ld, int64_t cand_use,
                                const float* q2d, int64_t rows, const int32_t* row_list,
                                int64_t n, int L, int64_t* idx, float* dist, int* flags,

@@ -49,40 +49,105 @@ __device__ void bitonic_sort(uint64_t* buf) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_select(const float* __restrict__ keys, int64_t ld,
-                                                     int64_t n, int L,
-                                                     const int32_t* __restrict__ row_list,
-                                                     int64_t exclude_base,
-                                                     uint64_t* __restrict__ out) {
-  __shared__ uint64_t buf[kSelectBuf];
-  const int64_t ri = blockIdx.x;
-  const int64_t b = row_list ? (int64_t)row_list[ri] : ri;
-  const float* kr = keys + b * ld;
-  const int64_t excl = exclude_base >= 0 ? exclude_base + b : -1;
-  for (int i = threadIdx.x; i < kSelectBuf; i += kThreads) buf[i] = ~0ull;
-  const int fill = kSelectBuf - L;
-  for (int64_t s0 = 0; s0 < n; s0 += fill) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < fill; i += kThreads) {
-      const int64_t u = s0 + i;
-      uint64_t kk = ~0ull;
-      if (u < n && u != excl) kk = pack_s(kr[u], (uint32_t)u);
-      buf[L + i] = kk;
-    }
-    __syncthreads();
-    bitonic_sort<kSelectBuf>(buf);
+// Threshold selection of the L smallest keys of one part of a row.  The
+// buffer holds the best L keys found so far (sorted, at the front) followed
+// by unsorted newcomers; a key enters only if it beats the L-th best at the
+// last compaction, so after the first few thousand keys almost nothing is
+// inserted and the pass runs at the speed of the coalesced reads.  A
+// compaction (bitonic sort of the buffer) runs when the next round of reads
+// could overflow it.  Keys are unique (row index in the low bits), so the
+// result is the exact L smallest in (distance, index) order.
+constexpr int kSelBuf = 4096;
+constexpr int kSelPer = 8;                      // keys per thread per round
+constexpr int kSelRound = kSelPer * kThreads;   // 2048
+constexpr int64_t kSelPart = 32768;             // keys per workgroup in the first pass
+
+__device__ __forceinline__ void sel_compact(uint64_t* buf, int* cnt, uint64_t* thr, int L) {
+  bitonic_sort<kSelBuf>(buf);  // entries at or past *cnt are ~0 and stay at the back
+  const int old = *cnt, keep = min(old, L);
+  __syncthreads();
+  for (int i = keep + (int)threadIdx.x; i < old; i += kThreads) buf[i] = ~0ull;
+  if (threadIdx.x == 0) {
+    *cnt = keep;
+    *thr = keep >= L ? buf[L - 1] : ~0ull;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < L; i += kThreads) out[ri * L + i] = buf[i];
+}
+
+// PACKED: keys are already packed (a second pass over first-pass results);
+// otherwise float32 distances of row b, packed with their index here.
+template <bool PACKED>
+__global__ __launch_bounds__(kThreads) void k_select(const void* __restrict__ keys_, int64_t ld,
+                                                     int64_t n, int L,
+                                                     const int32_t* __restrict__ row_list,
+                                                     int64_t exclude_base, int64_t part_len,
+                                                     uint64_t* __restrict__ out) {
+  __shared__ uint64_t buf[kSelBuf];
+  __shared__ int cnt;
+  __shared__ uint64_t thr;
+  const int64_t ri = blockIdx.x, part = blockIdx.y;
+  const int64_t b = row_list ? (int64_t)row_list[ri] : ri;
+  const int64_t excl = exclude_base >= 0 ? exclude_base + b : -1;
+  const int64_t lo = part * part_len, hi = min(n, lo + part_len);
+  const float* kf = (const float*)keys_ + (PACKED ? 0 : b * ld);
+  const uint64_t* kp = (const uint64_t*)keys_ + (PACKED ? ri * ld : 0);
+  for (int i = threadIdx.x; i < kSelBuf; i += kThreads) buf[i] = ~0ull;
+  if (threadIdx.x == 0) {
+    cnt = 0;
+    thr = ~0ull;
+  }
+  __syncthreads();
+  for (int64_t base = lo; base < hi; base += kSelRound) {
+    const int c = cnt;
+    __syncthreads();  // every thread has read cnt before any append below
+    if (c > kSelBuf - kSelRound) sel_compact(buf, &cnt, &thr, L);
+    const uint64_t t = thr;
+    uint64_t kk[kSelPer];
+#pragma unroll
+    for (int e = 0; e < kSelPer; ++e) {
+      const int64_t u = base + e * kThreads + threadIdx.x;
+      kk[e] = ~0ull;
+      if (u < hi) {
+        if constexpr (PACKED) kk[e] = kp[u];
+        else if (u != excl) kk[e] = pack_s(kf[u], (uint32_t)u);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kSelPer; ++e)
+      if (kk[e] < t) buf[atomicAdd(&cnt, 1)] = kk[e];
+    __syncthreads();
+  }
+  sel_compact(buf, &cnt, &thr, L);
+  uint64_t* o = out + (ri * gridDim.y + part) * (int64_t)L;
+  for (int i = threadIdx.x; i < L; i += kThreads) o[i] = buf[i];
+}
+
+int64_t select_parts(int64_t n) { return n > kSelPart ? (n + kSelPart - 1) / kSelPart : 1; }
+
+int64_t select_tmp_elems(int64_t rows, int64_t n, int L) {
+  const int64_t P = select_parts(n);
+  return P > 1 ? rows * P * L : 0;
 }
 
 hipError_t launch_select(const float* keys, int64_t ld, int64_t n, int64_t rows, int L,
                          const int32_t* row_list, int64_t exclude_base, uint64_t* out,
-                         hipStream_t s) {
+                         uint64_t* tmp, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  if (L < 1 || L > kSelectBuf / 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_select, dim3((unsigned)rows), dim3(kThreads), 0, s, keys, ld, n, L,
-                     row_list, exclude_base, out);
+  if (L < 1 || L > kSelectBuf / 2 || rows > 0x7fffffffLL) return hipErrorInvalidValue;
+  const int64_t P = select_parts(n);
+  if (P == 1) {
+    hipLaunchKernelGGL(k_select<false>, dim3((unsigned)rows, 1), dim3(kThreads), 0, s,
+                       (const void*)keys, ld, n, L, row_list, exclude_base, n > 0 ? n : 1, out);
+    return hipGetLastError();
+  }
+  if (!tmp || P > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_select<false>, dim3((unsigned)rows, (unsigned)P), dim3(kThreads), 0, s,
+                     (const void*)keys, ld, n, L, row_list, exclude_base, kSelPart, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n2 = P * L;
+  hipLaunchKernelGGL(k_select<true>, dim3((unsigned)rows, 1), dim3(kThreads), 0, s,
+                     (const void*)tmp, n2, n2, L, nullptr, (int64_t)-1, n2, out);
   return hipGetLastError();
 }
 

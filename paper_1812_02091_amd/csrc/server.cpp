@@ -68,6 +68,7 @@ struct Lane {
   float2* ZW = nullptr;
   float* d2q = nullptr;
   uint64_t* cand = nullptr;
+  uint64_t* seltmp = nullptr;
   float* q2dv = nullptr;
   float* partial = nullptr;
   int64_t* idx = nullptr;
@@ -135,7 +136,7 @@ int halloc(lcemd_ctx* c, T*& p, size_t count) {
 
 void free_lane(Lane& L) {
   if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
-  void* dev[] = {L.qptr, L.qcol, L.qval, L.nq, L.ints, L.fixl, L.ZW, L.d2q, L.cand, L.q2dv, L.partial, L.idx, L.dist, L.flags};
+  void* dev[] = {L.qptr, L.qcol, L.qval, L.nq, L.ints, L.fixl, L.ZW, L.d2q, L.cand, L.seltmp, L.q2dv, L.partial, L.idx, L.dist, L.flags};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {L.h_qptr, L.h_qcol, L.h_qval, L.h_nq, L.h_idx, L.h_dist, L.h_flags, L.h_ints};
@@ -191,7 +192,7 @@ int issue(lcemd_server* s, Lane& L) {
     if (s->prec != LCEMD_FP32) HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
     HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, L.ZW, c->v_used, s->KT, L.nq, L.d2q,
                                        c->n, L.ints, kPersistBlocks, L.stream));
-    HIPCHK(c, launch_select(L.d2q, c->n, c->n, s->B, s->cld, nullptr, -1, L.cand, L.stream));
+    HIPCHK(c, launch_select(L.d2q, c->n, c->n, s->B, s->cld, nullptr, -1, L.cand, L.seltmp, L.stream));
     P1Args p = a;
     p.ZW = nullptr;
     p.fix_count = nullptr;
@@ -222,6 +223,7 @@ int setup_lane(lcemd_server* s, Lane& L) {
       (rc = dalloc(c, L.ints, 16, "lane")) || (rc = dalloc(c, L.fixl, kFixCapLane, "lane")) ||
       (rc = dalloc(c, L.ZW, B * c->v_used * s->KT, "lane tables")) ||
       (rc = dalloc(c, L.d2q, B * n, "lane")) || (rc = dalloc(c, L.cand, B * s->cld, "lane")) ||
+      (rc = dalloc(c, L.seltmp, select_tmp_elems(B, n, s->cld), "lane")) ||
       (rc = dalloc(c, L.q2dv, B * s->use, "lane")) ||
       (rc = dalloc(c, L.partial, B * s->use * rbcap, "lane")) ||
       (rc = dalloc(c, L.idx, B * s->l, "lane")) || (rc = dalloc(c, L.dist, B * s->l, "lane")) ||
@@ -428,7 +430,6 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   s->use = (int)std::min<int64_t>(std::max(4 * cfg->l, 64), c->n);
   s->cld = s->use < c->n ? s->use + 1 : s->use;
   if (s->cld > kSelectBuf / 2) s->use = kSelectBuf / 2 - 1, s->cld = s->use + 1;
-  s->W = std::max(cfg->max_batch_words, (int32_t)LCEMD_MAX_HIST);
   // admission by device memory: lanes x slots x per-query state <= budget
   const int nlanes = cfg->use_graph ? 2 : 1;
   s->continuous = nlanes > 1;
@@ -442,6 +443,8 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
                 (long long)budget, per_q);
   }
   s->B = (int)std::min<int64_t>(cfg->max_slots, fit);
+  s->W = cfg->max_batch_words > 0 ? std::max(cfg->max_batch_words, (int32_t)LCEMD_MAX_HIST)
+                                   : s->B * LCEMD_MAX_HIST;
   s->lanes.resize(nlanes);
   for (Lane& L : s->lanes) {
     if ((rc = setup_lane(s, L))) {

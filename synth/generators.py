@@ -105,41 +105,95 @@ def _zipf_cdf(v: int, s: float) -> np.ndarray:
     return cdf / cdf[-1]
 
 
-def _distinct_words(rng, cdf: np.ndarray, lengths: np.ndarray, chunk: int = 4096):
-    """For each row, the first L distinct word ids (in draw order) of i.i.d.
-    Zipf draws, returned sorted.  Draws 3*max(L) tokens per row of a chunk and
-    tops up the rare rows that still fall short."""
+class _ZipfSampler:
+    """Inverse-CDF sampling of word ranks: the same result as
+    searchsorted(cdf, u, side="right"), found from a guide table of the
+    CDF at K evenly spaced points and a short walk."""
+
+    def __init__(self, cdf: np.ndarray):
+        self.cdf = cdf
+        self.K = 4 * cdf.shape[0]
+        self.g = np.searchsorted(cdf, np.arange(self.K + 1) / self.K, side="right")
+
+    def __call__(self, u: np.ndarray) -> np.ndarray:
+        cdf, v = self.cdf, self.cdf.shape[0]
+        shape = u.shape
+        u = u.reshape(-1)
+        idx = self.g[np.minimum((u * self.K).astype(np.int64), self.K)]
+        np.minimum(idx, v - 1, out=idx)
+        act = np.nonzero(cdf[idx] <= u)[0]
+        while act.size:  # walk up to the first cdf entry above u
+            idx[act] += 1
+            act = act[(idx[act] < v - 1) & (cdf[idx[act]] <= u[act])]
+        act = np.nonzero((idx > 0) & (cdf[np.maximum(idx - 1, 0)] > u))[0]
+        while act.size:  # (u*K rounded up) walk down
+            idx[act] -= 1
+            act = act[(idx[act] > 0) & (cdf[idx[act] - 1] > u[act])]
+        return idx.reshape(shape)
+
+
+def _first_distinct(T: np.ndarray, L: np.ndarray) -> np.ndarray:
+    """Mask of the first L[r] distinct values of each row of T, in draw order."""
+    order = np.argsort(T, axis=1, kind="stable")
+    st = np.take_along_axis(T, order, 1)
+    fs = np.ones_like(st, dtype=bool)
+    fs[:, 1:] = st[:, 1:] != st[:, :-1]
+    first = np.empty_like(fs)
+    np.put_along_axis(first, order, fs, 1)
+    return first & (np.cumsum(first, axis=1) <= L[:, None])
+
+
+def _distinct_words(rng, cdf: np.ndarray, lengths: np.ndarray, chunk: int = 8192,
+                    threads: int = 8):
+    """For each row, the first L distinct word ids of i.i.d. Zipf draws,
+    returned sorted.  Rows are processed in groups of similar length (each
+    group with its own generator seeded from ``rng``, so the result does not
+    depend on the thread count); a group draws 2*max(L)+16 tokens per row
+    and redraws the rare rows that fall short with twice as many."""
     n = lengths.shape[0]
+    v = cdf.shape[0]
+    if n and int(lengths.max()) > v:
+        raise ValueError("a row asks for more distinct words than the vocabulary has")
     rowptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(lengths, out=rowptr[1:])
     cols = np.empty(int(rowptr[-1]), dtype=np.int32)
-    v = cdf.shape[0]
-    for a in range(0, n, chunk):
-        b = min(n, a + chunk)
-        L = lengths[a:b]
-        M = int(3 * L.max())
-        T = np.searchsorted(cdf, rng.random((b - a, M)), side="right").astype(np.int32)
-        np.minimum(T, v - 1, out=T)
-        order = np.argsort(T, axis=1, kind="stable")
-        st = np.take_along_axis(T, order, 1)
-        fs = np.ones_like(st, dtype=bool)
-        fs[:, 1:] = st[:, 1:] != st[:, :-1]
-        first = np.empty_like(fs)
-        np.put_along_axis(first, order, fs, 1)
-        rank = np.cumsum(first, axis=1)
-        keep = first & (rank <= L[:, None])
-        for r in range(b - a):
-            ids = T[r][keep[r]]
-            if ids.shape[0] < L[r]:  # rare: top up with more draws
-                seen = list(dict.fromkeys(T[r].tolist()))
-                while len(seen) < L[r]:
-                    extra = np.searchsorted(cdf, rng.random(int(L[r])), side="right")
-                    for t in np.minimum(extra, v - 1).tolist():
-                        if t not in seen:
-                            seen.append(t)
-                ids = np.array(seen[: L[r]], dtype=np.int32)
-            g = a + r
-            cols[rowptr[g]:rowptr[g + 1]] = np.sort(ids)
+    sample = _ZipfSampler(cdf)
+    order = np.argsort(lengths, kind="stable")
+    starts = list(range(0, n, chunk))
+    seeds = rng.integers(0, 2**63 - 1, len(starts))
+
+    def group(gi):
+        rows = order[starts[gi]:starts[gi] + chunk]
+        L = lengths[rows]
+        crng = np.random.default_rng(int(seeds[gi]))
+        todo = np.arange(rows.shape[0])
+        M = 2 * int(L.max()) + 16
+        while todo.size:
+            Lt = L[todo]
+            T = sample(crng.random((todo.size, M)))
+            keep = _first_distinct(T, Lt)
+            full = keep.sum(1) == Lt
+            r_loc, c_loc = np.nonzero(keep[full])
+            ids = T[full][r_loc, c_loc]
+            key = r_loc.astype(np.int64) * v + ids
+            key.sort()
+            r_s = key // v
+            done = todo[full]
+            off = np.zeros(done.size + 1, dtype=np.int64)
+            np.cumsum(L[done], out=off[1:])
+            dest = rowptr[rows[done]][r_s] + (np.arange(key.size) - off[r_s])
+            cols[dest] = (key - r_s * v).astype(np.int32)
+            todo = todo[~full]
+            M *= 2
+
+    if threads > 1 and len(starts) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+
+        with ThreadPoolExecutor(min(threads, len(starts))) as ex:
+            list(ex.map(group, range(len(starts))))
+    else:
+        for gi in range(len(starts)):
+            group(gi)
     return rowptr, cols
 
 

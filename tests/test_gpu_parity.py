@@ -315,3 +315,28 @@ def test_other_phase1_kernels(L, force, monkeypatch):
         qc, qw = w.queries.row(b)
         So, Zo, Wo, R = orc.tables(qc, qw, 4)
         P.check_table_rows(S[b], Z[b], W[b], So, R, qw, 4, qc.size)
+
+
+@pytest.mark.parametrize("direction,ell", [("d2q", 16), ("d2q", 1000), ("sym", 16), ("sym", 200)])
+def test_topl_many_documents(L, direction, ell):
+    """More database rows than one selection workgroup takes (two-pass
+    selection): the top-l equals the first l of the full distance row
+    ordered by (distance, index), bit for bit, and its distances match the
+    oracle pair by pair."""
+    w = make_workload("text", n=70000, B=3, v=3000)
+    ctx = _ctx(L, w)
+    say(f"[gpu] top-{ell} {direction} over n=70000 (two-pass selection)")
+    excl = 40000  # query b excludes row excl + b, which sits in the second part
+    idx, dist = ctx.topl(*_q(w), ell, method="act", k=4, direction=direction, exclude_self=excl)
+    full = ctx.distances(*_q(w), method="act", k=4, direction=direction)
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    for b in range(w.queries.n):
+        row = full[b].astype(np.float64).copy()
+        row[excl + b] = np.inf
+        order = np.lexsort((np.arange(row.size), row))[:ell]
+        assert np.array_equal(idx[b], order), b
+        assert np.array_equal(dist[b], full[b][order]), b
+        qc, qw = w.queries.row(b)
+        for j in range(0, ell, max(1, ell // 8)):
+            o = orc.pair(qc, qw, int(idx[b, j]), "act", 4, direction)
+            assert abs(float(dist[b, j]) - o) <= 1e-5 * abs(o) + 1e-7, (b, j)

@@ -46,3 +46,28 @@ def test_arrival_trace():
     assert np.all(np.diff(t) > 0) and q.n == 200
     L = q.lengths()
     assert L.min() >= 10 and L.max() <= 500
+
+
+def test_zipf_sampler_is_inverse_cdf():
+    """The guide-table sampler returns exactly searchsorted(cdf, u, 'right'),
+    also at CDF values and just below them."""
+    from synth.generators import _ZipfSampler, _zipf_cdf
+
+    for v, s in ((2000, 1.1), (70000, 1.0)):
+        cdf = _zipf_cdf(v, s)
+        u = np.random.default_rng(v).random((50, 200))
+        u[0, :6] = [0.0, cdf[0], cdf[10], np.nextafter(cdf[10], 0), cdf[-2], np.nextafter(1.0, 0)]
+        assert np.array_equal(_ZipfSampler(cdf)(u), np.searchsorted(cdf, u, side="right"))
+
+
+def test_distinct_words_independent_of_threads():
+    from synth.generators import _distinct_words, _zipf_cdf
+
+    cdf = _zipf_cdf(300, 1.0)
+    lengths = np.random.default_rng(3).integers(1, 300, 3000)
+    a = _distinct_words(np.random.default_rng(9), cdf, lengths, chunk=256, threads=1)
+    b = _distinct_words(np.random.default_rng(9), cdf, lengths, chunk=256, threads=4)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for r in range(0, 3000, 13):
+        c = a[1][a[0][r]:a[0][r + 1]]
+        assert c.size == lengths[r] and np.all(np.diff(c) > 0) and c.max() < 300
