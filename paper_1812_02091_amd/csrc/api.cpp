@@ -254,6 +254,10 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
   // bf16 keys carry an exactness certificate only on the 128-row kernel;
   // deeper lists use float32 keys
   if (prec != LCEMD_FP32 && (depth + kMargin > 32 || c->force_kernel || mode == P1_PAIR)) prec = LCEMD_FP32;
+  if (!a.work_ctr) {
+    int rc = wsget(c, "p1_counters", 8, a.work_ctr);
+    if (rc) return rc;
+  }
   const int margin = prec == LCEMD_FP32 ? 0 : kMargin;
   a.Vb = c->Vb;
   if (depth + margin <= 32 && !c->force_kernel) {
@@ -374,7 +378,10 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     }
     const double a2 = (double)nq * (8.0 * c->nnz + 8.0 * (c->n + 1) + 8.0 * (double)c->v_used * KT + 4.0 * c->n);
     if ((rc = prof_begin(c, "phase2", a2))) return rc;
-    HIPCHK(c, launch_phase2(c->xptr, c->xcv, c->n, ZW, c->v_used, KT, nq, out + q0 * ld, ld, c->stream));
+    unsigned long long* p2c;
+    if ((rc = wsget(c, "p2_counters", 8, p2c))) return rc;
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, ZW, c->v_used, KT, nq, nullptr,
+                                       out + q0 * ld, ld, p2c, c->stream));
     if ((rc = prof_end(c))) return rc;
     q0 += nq;
     prec = o->precision;

@@ -78,6 +78,9 @@ struct P1Args {
   int* fix_count;         // bf16 table modes: rows whose exactness certificate failed ...
   int64_t* fix_list;      // ... are appended here (flat table row index) for k_fix_rows
   int fix_cap;
+  // persistent kernels: eight work counters (one per XCD), zeroed by the
+  // launcher on its stream before the kernel
+  unsigned long long* work_ctr;
 };
 
 // kernel launchers (each in the translation unit of its kernel)
@@ -116,9 +119,13 @@ hipError_t launch_unpack_topl(const uint64_t* cand, int64_t cand_ld, int64_t row
                               hipStream_t s);
 hipError_t launch_max_inplace(float* a, const float* b, int64_t count, hipStream_t s);
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
+// Resident workgroups per CU for a kernel (cached) and the CU count.
+int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t items);
+// Phase 2 on a persistent grid: the query count is nq_dev[0] when nq_dev is
+// not null (fixed-shape batches), else nq.  counters: 8 u64, zeroed here.
 hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n,
-                                    const float2* ZW, int64_t v_used, int KT, const int* nq_dev,
-                                    float* out, int64_t ld, int* counters, int blocks,
-                                    hipStream_t s);
+                                    const float2* ZW, int64_t v_used, int KT, int64_t nq,
+                                    const int* nq_dev, float* out, int64_t ld,
+                                    unsigned long long* counters, hipStream_t s);
 
 }  // namespace lcemd

@@ -23,9 +23,11 @@
 // 2^-7 * 1.0625 * |v||c| (float32 accumulation included for m <= 4096);
 // the list therefore keeps, past the cut, every candidate whose key is
 // within 2^-6 * 1.07 * |v| * max|c| of the cut key: in exact order nothing
-// outside that band can precede the cut.  All listed candidates are then
-// recomputed exactly in float32 (the segment's vectors staged through LDS
-// 8 dims at a time), re-sorted and cut again.
+// outside that band can precede the cut.  All listed candidates then get
+// float32 distances -- |v|^2 + |c|^2 - 2<v, c> with the dot product
+// accumulated in float32 over the original vectors (staged through LDS a
+// chunk of dims at a time), or by direct differences where cancellation
+// could bite, as for float32 keys -- and are re-sorted and cut again.
 #include "internal.h"
 
 namespace lcemd {
@@ -39,8 +41,7 @@ constexpr int kWR = 128;        // rows per workgroup
 constexpr int kWC = 128;        // columns per MFMA pass
 constexpr int kStride = 144;    // bytes per staged column slice (128 + 16 pad)
 constexpr int kCK = 66;         // floats per key row (64 columns + 2 pad)
-constexpr int kQD = 8;          // dims per exact-recompute chunk
-constexpr int kQS = 12;         // floats per staged segment vector (8 dims + 4 pad)
+constexpr int kQSCap = kWR * kCK;  // floats of the staging area (the key buffer's size)
 constexpr int kSeg = LCEMD_MAX_HIST;
 constexpr int kGroupW = 8;      // queries per tile group (table modes)
 constexpr float kGuardW = 0.25f;
@@ -144,7 +145,7 @@ struct WideSmem {
   union {
     unsigned char st[kWC * kStride];  // staged column slice
     float ck[kWR * kCK];              // keys of 64 columns of a pass
-    float qs[PREC == PREC_F32 ? 1 : kSeg * kQS];  // segment vectors, 8 dims (exact recompute)
+    float qs[PREC == PREC_F32 ? 1 : kQSCap];  // segment vectors, a chunk of dims (exact recompute)
     float zb[kWR * (KL + 1)];         // exact squared distances of the lists
   } u;
   uint64_t lst[2][kWR * (KL + 1)];  // row stride KL + 1 spreads rows over LDS banks
@@ -161,12 +162,54 @@ struct WideSmem {
   float qmax;
 };
 
+// Float32 dot products <v_row, c_pos> of a thread's listed candidates
+// (ex[e] for list entry sub + 2e), D dims at a time: the row's D dims are
+// loaded into registers before the barrier, the segment's vectors are
+// staged in LDS (row stride D + 4 floats).  Dims are accumulated in order.
+template <int D, int KH>
+__device__ __forceinline__ void wide_dots(float (&ex)[KH], const int (&ps)[KH], int len, int sub,
+                                          bool row_ok, const float* __restrict__ vr,
+                                          const P1Args& a, float* qs, const int* cid, int h,
+                                          int tid) {
+  constexpr int D4 = D / 4, QS = D + 4;
+  for (int d0 = 0; d0 < a.m_pad; d0 += D) {
+    float4 v[D4];
+#pragma unroll
+    for (int q = 0; q < D4; ++q) v[q] = row_ok ? *(const float4*)(vr + d0 + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    for (int f = tid; f < h * D4; f += kThreads) {
+      const int c = f / D4, q = f % D4;
+      *(float4*)(&qs[c * QS + q * 4]) = *(const float4*)(a.V + (size_t)cid[c] * a.m_pad + d0 + q * 4);
+    }
+    __syncthreads();
+    if (row_ok) {
+#pragma unroll
+      for (int e = 0; e < KH; ++e) {
+        if (sub + 2 * e < len) {
+          const float* cp = &qs[ps[e] * QS];
+          float s = ex[e];
+#pragma unroll
+          for (int q = 0; q < D4; ++q) {
+            const float4 c = *(const float4*)(cp + 4 * q);
+            s = fmaf(v[q].x, c.x, s);
+            s = fmaf(v[q].y, c.y, s);
+            s = fmaf(v[q].z, c.z, s);
+            s = fmaf(v[q].w, c.w, s);
+          }
+          ex[e] = s;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
+// One work item: (query, 128-row block) in the table modes, (pair, row
+// block) in pair mode.  Returns early (uniformly) for empty items.
 template <int MODE, int KL, int PREC>
-__global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a) {
+__device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_raw, int64_t item) {
   using Sm = WideSmem<KL, PREC>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   Sm& sm = *reinterpret_cast<Sm*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -175,8 +218,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a) {
   int64_t out_row0 = 0, pidx = 0;
   int rb = 0;
   if constexpr (MODE == P1_PAIR) {
-    pidx = blockIdx.x;
-    rb = blockIdx.y;
+    pidx = item / a.rb_max;
+    rb = (int)(item % a.rb_max);
     int64_t b, u;
     if (a.cand) {
       const int64_t qi = pidx / a.cand_use, c = pidx % a.cand_use;
@@ -214,12 +257,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a) {
       sm.qn[c] = a.vnorm[w];
     }
   } else {
+    // items run query-fastest within a group of kGroupW queries, then row
+    // block, then group: an XCD's contiguous range of items keeps a group's
+    // query vectors and a row block's vectors in its L2
     const int64_t nrb = (a.v_used + kWR - 1) / kWR;
-    const int64_t ngroups = (a.nq + kGroupW - 1) / kGroupW;
-    const int64_t total = ngroups * nrb * kGroupW;
-    const int64_t per = (int64_t)gridDim.x / 8;
-    const int64_t work = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (work >= total) return;
+    const int64_t work = item;
     const int64_t qin = work % kGroupW, t = work / kGroupW;
     const int64_t rblk = t % nrb, g = t / nrb;
     const int64_t qi = g * kGroupW + qin;
@@ -430,29 +472,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a) {
       ps[e] = l < len ? (int)(uint32_t)L[l] : 0;
     }
     const float* vr = a.V + (size_t)sm.rid[row] * a.m_pad;
-    for (int d0 = 0; d0 < a.m_pad; d0 += kQD) {
-      __syncthreads();
-      for (int f = tid; f < h * 2; f += kThreads) {
-        const int c = f >> 1, q = f & 1;
-        *(float4*)(&sm.u.qs[c * kQS + q * 4]) = *(const float4*)(a.V + (size_t)sm.cid[c] * a.m_pad + d0 + q * 4);
-      }
-      __syncthreads();
-      if (row_ok) {
-        const float4 v0 = *(const float4*)(vr + d0), v1 = *(const float4*)(vr + d0 + 4);
+    // chunks of D dims of all h segment vectors per LDS pass, as wide as
+    // the staging area allows (fewer passes and barriers)
+    if (h * 68 <= kQSCap && a.m_pad % 64 == 0)
+      wide_dots<64, KH>(ex, ps, len, sub, row_ok, vr, a, sm.u.qs, sm.cid, h, tid);
+    else if (h * 36 <= kQSCap && a.m_pad % 32 == 0)
+      wide_dots<32, KH>(ex, ps, len, sub, row_ok, vr, a, sm.u.qs, sm.cid, h, tid);
+    else if (h * 20 <= kQSCap && a.m_pad % 16 == 0)
+      wide_dots<16, KH>(ex, ps, len, sub, row_ok, vr, a, sm.u.qs, sm.cid, h, tid);
+    else
+      wide_dots<8, KH>(ex, ps, len, sub, row_ok, vr, a, sm.u.qs, sm.cid, h, tid);
+    // squared distances from the float32 dot products; where cancellation
+    // could bite, by direct differences (as for float32 keys)
 #pragma unroll
-        for (int e = 0; e < KH; ++e) {
-          if (sub + 2 * e < len) {
-            const float4* qp = (const float4*)(&sm.u.qs[ps[e] * kQS]);
-            const float4 q0 = qp[0], q1 = qp[1];
-            float s = ex[e];
-            float dd;
-            dd = v0.x - q0.x; s = fmaf(dd, dd, s); dd = v0.y - q0.y; s = fmaf(dd, dd, s);
-            dd = v0.z - q0.z; s = fmaf(dd, dd, s); dd = v0.w - q0.w; s = fmaf(dd, dd, s);
-            dd = v1.x - q1.x; s = fmaf(dd, dd, s); dd = v1.y - q1.y; s = fmaf(dd, dd, s);
-            dd = v1.z - q1.z; s = fmaf(dd, dd, s); dd = v1.w - q1.w; s = fmaf(dd, dd, s);
-            ex[e] = s;
-          }
-        }
+    for (int e = 0; e < KH; ++e) {
+      if (row_ok && sub + 2 * e < len) {
+        const float qn = sm.qn[ps[e]];
+        float d2 = (sm.rvn[row] + qn) - 2.f * ex[e];
+        if (!(d2 >= kGuardW * (sm.rvn[row] + qn))) d2 = w_exact_d2(a.V, a.m_pad, sm.rid[row], sm.cid[ps[e]]);
+        ex[e] = d2;
       }
     }
     __syncthreads();
@@ -554,23 +592,46 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a) {
   }
 }
 
+// Persistent grid: as many workgroups as stay resident, each pulling items
+// from the counter of its XCD (workgroup i runs on XCD i % 8), which walks a
+// contiguous eighth of the items.  No workgroup waits on another; each
+// exits once its counter passes the end of its range.
+template <int MODE, int KL, int PREC>
+__global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a, int64_t total) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int64_t s_item;
+  const int xcd = blockIdx.x & 7;
+  const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
+  while (true) {
+    __syncthreads();  // the previous item is done with LDS and s_item
+    if (threadIdx.x == 0) s_item = lo + (int64_t)atomicAdd(&a.work_ctr[xcd], 1ull);
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= hi) break;
+    wide_task<MODE, KL, PREC>(a, smem_raw, item);
+  }
+}
+
 template <int MODE, int KL, int PREC>
 static hipError_t launch_wide_one(const P1Args& a, hipStream_t s) {
   const size_t shmem = sizeof(WideSmem<KL, PREC>);
-  hipError_t e = hipFuncSetAttribute((const void*)k_phase1_wide<MODE, KL, PREC>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  const void* fn = (const void*)k_phase1_wide<MODE, KL, PREC>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
-  dim3 grid;
+  int64_t total;
   if (MODE == P1_PAIR) {
-    grid = dim3((unsigned)a.npairs, (unsigned)a.rb_max, 1);
+    total = a.npairs * (int64_t)a.rb_max;
   } else {
     const int64_t nrb = (a.v_used + kWR - 1) / kWR;
-    const int64_t total = (a.nq + kGroupW - 1) / kGroupW * nrb * kGroupW;
-    const int64_t blocks = (total + 7) / 8 * 8;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    grid = dim3((unsigned)blocks, 1, 1);
+    total = (a.nq + kGroupW - 1) / kGroupW * nrb * kGroupW;
   }
-  hipLaunchKernelGGL((k_phase1_wide<MODE, KL, PREC>), grid, dim3(kThreads), shmem, s, a);
+  if (total <= 0) return hipSuccess;
+  if (!a.work_ctr) return hipErrorInvalidValue;
+  e = launch_zero_ints((int*)a.work_ctr, 16, s);
+  if (e != hipSuccess) return e;
+  const int grid = persistent_grid(fn, kThreads, shmem, total);
+  if (grid <= 0) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_phase1_wide<MODE, KL, PREC>), dim3(grid), dim3(kThreads), shmem, s, a, total);
   return hipGetLastError();
 }
 

@@ -11,6 +11,11 @@
 // apply QB queries' tables to each non-zero, then reduce across the wave
 // with a fixed butterfly.  The per-row sum therefore has a fixed order that
 // does not depend on which other queries or rows share the launch.
+#include <algorithm>
+#include <climits>
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
 
 namespace lcemd {
@@ -18,6 +23,7 @@ namespace lcemd {
 constexpr int kDocsPerWave = 4;
 constexpr int kDocsPerWG = kDocsPerWave * (kThreads / 64);
 constexpr int kQB = 4;
+constexpr int kItemDocs = 16;  // database rows per work item of the persistent kernel
 
 __device__ __forceinline__ float wave_sum(float t) {
   t += __shfl_xor(t, 32);
@@ -144,31 +150,33 @@ hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const 
   return hipGetLastError();
 }
 
-// Persistent variant for fixed-shape (graph-captured) batches: a fixed grid
-// whose waves pull (query group, 4 database rows) items from eight work
-// counters, one per XCD, each counter walking a contiguous eighth of the
-// items.  The live query count is read from device memory; every wave exits
-// once its counter passes the end of its range.
+// Persistent variant: a grid of resident workgroups whose waves pull
+// (query group, kItemDocs database rows) items from eight work counters, one per
+// XCD, each counter walking a contiguous eighth of the items (so an XCD
+// keeps a few queries' tables hot in its L2).  For fixed-shape batches the
+// live query count is read from device memory.  Every wave exits once its
+// counter passes the end of its range.
 template <bool EVEN>
 __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
     const int64_t* __restrict__ xptr, const int2* __restrict__ xcv, int64_t n,
-    const float2* __restrict__ ZW, int64_t v_used, int KT, const int* __restrict__ nq_dev,
-    float* __restrict__ out, int64_t ld, int* __restrict__ counters) {
+    const float2* __restrict__ ZW, int64_t v_used, int KT, int64_t nq_arg,
+    const int* __restrict__ nq_dev, float* __restrict__ out, int64_t ld,
+    unsigned long long* __restrict__ counters) {
   const int lane = threadIdx.x & 63;
   const int xcd = blockIdx.x & 7;
-  const int64_t nq = *nq_dev;
-  const int64_t nd4 = (n + 3) / 4;
+  const int64_t nq = nq_dev ? (int64_t)*nq_dev : nq_arg;
+  const int64_t nd4 = (n + kItemDocs - 1) / kItemDocs;
   const int64_t total = (nq + kQB - 1) / kQB * nd4;
   const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
   while (true) {
-    int it = 0;
-    if (lane == 0) it = atomicAdd(&counters[xcd], 1);
-    const int64_t item = lo + __shfl(it, 0);
+    unsigned long long it = 0;
+    if (lane == 0) it = atomicAdd(&counters[xcd], 1ull);
+    const int64_t item = lo + (int64_t)__shfl((long long)it, 0);
     if (item >= hi) break;
     const int64_t q0 = (item / nd4) * kQB;
     const int nqb = (int)min((int64_t)kQB, nq - q0);
-    const int64_t ubase = (item % nd4) * 4;
-    for (int j = 0; j < 4; ++j) {
+    const int64_t ubase = (item % nd4) * kItemDocs;
+    for (int j = 0; j < kItemDocs; ++j) {
       const int64_t u = ubase + j;
       if (u >= n) break;
       doc_costs<EVEN>(lane, u, q0, nqb, xptr, xcv, ZW, v_used, KT, out, ld);
@@ -186,18 +194,58 @@ hipError_t launch_zero_ints(int* p, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+struct OccEntry {
+  const void* fn;
+  size_t shmem;
+  int device;
+  int per_cu;
+};
+std::mutex g_occ_mu;
+std::vector<OccEntry> g_occ;
+int g_cus[64] = {0};
+}  // namespace
+
+int persistent_grid(const void* fn, int threads, size_t shmem, int64_t items) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+  int per_cu = -1;
+  {
+    std::lock_guard<std::mutex> g(g_occ_mu);
+    for (const OccEntry& e : g_occ)
+      if (e.fn == fn && e.shmem == shmem && e.device == dev) per_cu = e.per_cu;
+    if (!g_cus[dev] && hipDeviceGetAttribute(&g_cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return -1;
+    if (per_cu < 0) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shmem) != hipSuccess) return -1;
+      g_occ.push_back({fn, shmem, dev, per_cu});
+    }
+  }
+  if (per_cu < 1) return -1;
+  int64_t grid = (int64_t)per_cu * g_cus[dev];
+  grid = std::min<int64_t>(grid, (items + 7) / 8 * 8);
+  grid = std::max<int64_t>(8, (grid + 7) / 8 * 8);
+  return (int)grid;
+}
+
 hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n,
-                                    const float2* ZW, int64_t v_used, int KT, const int* nq_dev,
-                                    float* out, int64_t ld, int* counters, int blocks,
-                                    hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  blocks = (blocks + 7) / 8 * 8;
+                                    const float2* ZW, int64_t v_used, int KT, int64_t nq,
+                                    const int* nq_dev, float* out, int64_t ld,
+                                    unsigned long long* counters, hipStream_t s) {
+  if (n <= 0 || (!nq_dev && nq <= 0)) return hipSuccess;
+  hipError_t e = launch_zero_ints((int*)counters, 16, s);
+  if (e != hipSuccess) return e;
+  // items: bounded by the batch size the kernel can see
+  const int64_t items = nq_dev ? INT64_MAX / 2 : (nq + kQB - 1) / kQB * ((n + kItemDocs - 1) / kItemDocs) * 64;
+  const void* fn = KT % 2 == 0 ? (const void*)k_phase2_persistent<true> : (const void*)k_phase2_persistent<false>;
+  const int grid = persistent_grid(fn, kThreads, 0, items);
+  if (grid <= 0) return hipErrorInvalidConfiguration;
   if (KT % 2 == 0)
-    hipLaunchKernelGGL(k_phase2_persistent<true>, dim3(blocks), dim3(kThreads), 0, s, xptr, xcv, n,
-                       ZW, v_used, KT, nq_dev, out, ld, counters);
+    hipLaunchKernelGGL(k_phase2_persistent<true>, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n,
+                       ZW, v_used, KT, nq, nq_dev, out, ld, counters);
   else
-    hipLaunchKernelGGL(k_phase2_persistent<false>, dim3(blocks), dim3(kThreads), 0, s, xptr, xcv, n,
-                       ZW, v_used, KT, nq_dev, out, ld, counters);
+    hipLaunchKernelGGL(k_phase2_persistent<false>, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n,
+                       ZW, v_used, KT, nq, nq_dev, out, ld, counters);
   return hipGetLastError();
 }
 

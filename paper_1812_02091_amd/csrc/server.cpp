@@ -63,7 +63,8 @@ struct Lane {
   int32_t* qcol = nullptr;
   float* qval = nullptr;
   int* nq = nullptr;
-  int* ints = nullptr;  // [0..7] phase-2 work counters, [8] overflow, [9] rows to redo
+  int* ints = nullptr;  // [8] overflow, [9] rows to redo
+  unsigned long long* ctr = nullptr;  // work counters of the persistent kernels
   int64_t* fixl = nullptr;
   float2* ZW = nullptr;
   float* d2q = nullptr;
@@ -88,7 +89,6 @@ struct Lane {
 };
 
 constexpr int kFixCapLane = 1 << 16;
-constexpr int kPersistBlocks = 2048;
 constexpr int kFixBlocks = 256;
 
 }  // namespace
@@ -136,7 +136,7 @@ int halloc(lcemd_ctx* c, T*& p, size_t count) {
 
 void free_lane(Lane& L) {
   if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
-  void* dev[] = {L.qptr, L.qcol, L.qval, L.nq, L.ints, L.fixl, L.ZW, L.d2q, L.cand, L.seltmp, L.q2dv, L.partial, L.idx, L.dist, L.flags};
+  void* dev[] = {L.qptr, L.qcol, L.qval, L.nq, L.ints, L.ctr, L.fixl, L.ZW, L.d2q, L.cand, L.seltmp, L.q2dv, L.partial, L.idx, L.dist, L.flags};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {L.h_qptr, L.h_qcol, L.h_qval, L.h_nq, L.h_idx, L.h_dist, L.h_flags, L.h_ints};
@@ -183,6 +183,7 @@ int issue(lcemd_server* s, Lane& L) {
     a.KT = s->KT;
     a.ZW = L.ZW;
     a.overflow = L.ints + 8;
+    a.work_ctr = L.ctr;
     if (s->prec != LCEMD_FP32) {
       a.fix_count = L.ints + 9;
       a.fix_list = L.fixl;
@@ -190,8 +191,8 @@ int issue(lcemd_server* s, Lane& L) {
     }
     if ((rc = p1_launch(c, a, P1_TABLE, s->prec, s->KT, LCEMD_MAX_HIST, LCEMD_MAX_HIST))) break;
     if (s->prec != LCEMD_FP32) HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, L.ZW, c->v_used, s->KT, L.nq, L.d2q,
-                                       c->n, L.ints, kPersistBlocks, L.stream));
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, L.ZW, c->v_used, s->KT, s->B, L.nq,
+                                       L.d2q, c->n, L.ctr + 8, L.stream));
     HIPCHK(c, launch_select(L.d2q, c->n, c->n, s->B, s->cld, nullptr, -1, L.cand, L.seltmp, L.stream));
     P1Args p = a;
     p.ZW = nullptr;
@@ -220,7 +221,7 @@ int setup_lane(lcemd_server* s, Lane& L) {
   HIPCHK(c, hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
   if ((rc = dalloc(c, L.qptr, B + 1, "lane")) || (rc = dalloc(c, L.qcol, W, "lane")) ||
       (rc = dalloc(c, L.qval, W, "lane")) || (rc = dalloc(c, L.nq, 1, "lane")) ||
-      (rc = dalloc(c, L.ints, 16, "lane")) || (rc = dalloc(c, L.fixl, kFixCapLane, "lane")) ||
+      (rc = dalloc(c, L.ints, 16, "lane")) || (rc = dalloc(c, L.ctr, 16, "lane")) || (rc = dalloc(c, L.fixl, kFixCapLane, "lane")) ||
       (rc = dalloc(c, L.ZW, B * c->v_used * s->KT, "lane tables")) ||
       (rc = dalloc(c, L.d2q, B * n, "lane")) || (rc = dalloc(c, L.cand, B * s->cld, "lane")) ||
       (rc = dalloc(c, L.seltmp, select_tmp_elems(B, n, s->cld), "lane")) ||
