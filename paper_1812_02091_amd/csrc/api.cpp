@@ -328,17 +328,18 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
   if ((rc = wsget(c, "ovf", 1, ovf))) return rc;
   int64_t q0 = 0;
   while (q0 < Q.B) {
-    int64_t Bt = (int64_t)std::max<size_t>(1, c->table_budget / (per_q * KT));
+    int64_t Bt = (int64_t)std::max<size_t>(1, c->table_budget / (per_q * 2 * zw_pairs(KT)));
     Bt = std::min<int64_t>(Bt, 65535);
     const int64_t nq = std::min<int64_t>(Bt, Q.B - q0);
     float2* ZW;
-    if ((rc = wsget(c, "zw", (size_t)nq * c->v_used * KT, ZW))) return rc;
+    if ((rc = wsget(c, "zw", (size_t)nq * c->v_used * 2 * zw_pairs(KT), ZW))) return rc;
     HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
     P1Args a = base_args(c, Q, o);
     a.KT = KT;
     a.q0 = q0;
     a.nq = nq;
     a.ZW = ZW;
+    a.zw_nq = nq;
     a.overflow = ovf;
     int* fixc = nullptr;
     if (prec != LCEMD_FP32) {
@@ -380,7 +381,7 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     if ((rc = prof_begin(c, "phase2", a2))) return rc;
     unsigned long long* p2c;
     if ((rc = wsget(c, "p2_counters", 8, p2c))) return rc;
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, ZW, c->v_used, KT, nq, nullptr,
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, ZW, nq, KT, nq, nullptr,
                                        out + q0 * ld, ld, p2c, c->stream));
     if ((rc = prof_end(c))) return rc;
     q0 += nq;

@@ -69,7 +69,8 @@ struct P1Args {
   const int32_t* qlist;   // query ids for candidate mode (NULL: identity)
   int rb_max;             // row blocks per pair (grid y)
   // outputs
-  float2* ZW;             // P1_TABLE: [nq][v_used][KT]
+  float2* ZW;             // P1_TABLE: see zw_at
+  int64_t zw_nq;          // P1_TABLE: queries per table (the tile's or batch's slot count)
   int32_t* S;             // P1_TABLE_FULL: [nq][v_used][k]
   float* Z;
   float* W;
@@ -83,6 +84,29 @@ struct P1Args {
   unsigned long long* work_ctr;
 };
 
+// Table layout of P1_TABLE: entry l of query qi's row for used word r.
+// Entries go in pairs (2p, 2p + 1) of 16 bytes, and pair p of one word lies
+// next to pair p of the same word for every query of the table, so that
+// phase 2 reads a word's first pair for a group of queries as one
+// contiguous run: float2 index ((r * KP + p) * zw_nq + qi) * 2 + (l & 1),
+// KP = ceil(KT / 2).  Tables hold zw_nq * v_used * KP float4.
+__host__ __device__ inline int64_t zw_pairs(int KT) { return (KT + 1) >> 1; }
+__device__ __forceinline__ float4* zw_pair(float2* ZW, int64_t zw_nq, int KT, int64_t qi, int64_t r,
+                                           int p) {
+  return (float4*)ZW + (r * zw_pairs(KT) + p) * zw_nq + qi;
+}
+// Write the D entries (z_l, w_l) of one table row (pairs; an odd tail pair
+// gets zeros in its second half).
+template <typename ZF, typename WF>
+__device__ __forceinline__ void zw_write_row(float2* ZW, int64_t zw_nq, int KT, int64_t qi,
+                                             int64_t r, int D, ZF zf, WF wf) {
+  for (int l = 0; l < D && l < KT; l += 2) {
+    const bool two = l + 1 < D && l + 1 < KT;
+    *zw_pair(ZW, zw_nq, KT, qi, r, l >> 1) =
+        make_float4(zf(l), wf(l), two ? zf(l + 1) : 0.f, two ? wf(l + 1) : 0.f);
+  }
+}
+
 // kernel launchers (each in the translation unit of its kernel)
 hipError_t launch_phase1_deep(const P1Args& a, int mode, int hmax, int prec, hipStream_t s);
 hipError_t launch_phase1_fast(const P1Args& a, int mode, int KT, int prec, hipStream_t s);
@@ -91,9 +115,6 @@ int phase1_wide_rows();
 hipError_t launch_fix_rows(const P1Args& a, int mode, int count, hipStream_t s);
 hipError_t launch_pair_reduce(const float* partial, int64_t npairs, int rb_max, float* out,
                               int64_t out_ld, int64_t per_row, hipStream_t s);
-hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const float2* ZW,
-                         int64_t v_used, int KT, int64_t nq, float* out, int64_t ld,
-                         hipStream_t s);
 hipError_t launch_prep_embeddings(const float* Vin, int64_t v, int m, int m_pad, int l2norm,
                                   float* Vpad, float* vnorm, hipStream_t s);
 hipError_t launch_make_bf16(const float* V, int64_t count, uint16_t* out, hipStream_t s);
@@ -124,7 +145,7 @@ int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t items
 // Phase 2 on a persistent grid: the query count is nq_dev[0] when nq_dev is
 // not null (fixed-shape batches), else nq.  counters: 8 u64, zeroed here.
 hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n,
-                                    const float2* ZW, int64_t v_used, int KT, int64_t nq,
+                                    const float2* ZW, int64_t zw_nq, int KT, int64_t nq,
                                     const int* nq_dev, float* out, int64_t ld,
                                     unsigned long long* counters, hipStream_t s);
 

@@ -245,7 +245,9 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
       if constexpr (MODE == P1_TABLE) {
         const bool ovf = !stop && depth >= a.KT;
         if (sub == 0) {
-          a.ZW[(out_row0 + row) * a.KT + depth - 1] = make_float2(z, (stop || ovf) ? INFINITY : w);
+          const int64_t flat = out_row0 + row;
+          float2* pr = (float2*)zw_pair(a.ZW, a.zw_nq, a.KT, flat / a.v_used, flat % a.v_used, (depth - 1) >> 1);
+          pr[(depth - 1) & 1] = make_float2(z, (stop || ovf) ? INFINITY : w);
           if (ovf) a.overflow[0] = 1;
         }
         stop = stop || ovf;

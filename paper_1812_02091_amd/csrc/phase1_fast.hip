@@ -380,11 +380,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_fast(P1Args a) {
     }
     if (!covered && D < h && a.overflow) a.overflow[0] = 1;  // list too short (ICT only)
     if constexpr (MODE == P1_TABLE) {
-      float2* out = a.ZW + (out_row0 + row) * (int64_t)a.KT;
-      for (int l = 0; l < D && l < a.KT; ++l) {
-        const int pos = (int)(uint32_t)L[l];
-        out[l] = make_float2(sqrtf(fmaxf(Z2[l], 0.f)), l == D - 1 ? INFINITY : sm.cap[pos]);
-      }
+      const int64_t flat = out_row0 + row;
+      zw_write_row(a.ZW, a.zw_nq, a.KT, flat / a.v_used, flat % a.v_used, D,
+                   [&](int l) { return sqrtf(fmaxf(Z2[l], 0.f)); },
+                   [&](int l) { return l == D - 1 ? INFINITY : sm.cap[(uint32_t)L[l]]; });
       if (D > a.KT && a.overflow) a.overflow[0] = 1;
     } else if constexpr (MODE == P1_TABLE_FULL) {
       const int64_t o0 = (out_row0 + row) * (int64_t)a.k;

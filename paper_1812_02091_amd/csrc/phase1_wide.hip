@@ -551,11 +551,10 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       }
     }
     if constexpr (MODE == P1_TABLE) {
-      float2* out = a.ZW + (out_row0 + row) * (int64_t)a.KT;
-      for (int l = 0; l < D && l < a.KT; ++l) {
-        const int pos = (int)(uint32_t)Lw[l];
-        out[l] = make_float2(sqrtf(fmaxf(Z2[l], 0.f)), l == D - 1 ? INFINITY : sm.cap[pos]);
-      }
+      const int64_t flat = out_row0 + row;
+      zw_write_row(a.ZW, a.zw_nq, a.KT, flat / a.v_used, flat % a.v_used, D,
+                   [&](int l) { return sqrtf(fmaxf(Z2[l], 0.f)); },
+                   [&](int l) { return l == D - 1 ? INFINITY : sm.cap[(uint32_t)Lw[l]]; });
       if (D > a.KT && a.overflow) a.overflow[0] = 1;
     } else if constexpr (MODE == P1_TABLE_FULL) {
       const int64_t o0 = (out_row0 + row) * (int64_t)a.k;
@@ -730,11 +729,9 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
     if (D > a.KT) {
       a.overflow[0] = 1;
     } else {
-      float2* out = a.ZW + flat * (int64_t)a.KT;
-      for (int l = 0; l < D; ++l) {
-        const int pos = (int)(uint32_t)keys[l];
-        out[l] = make_float2(sqrtf(fmaxf(w_unpack(keys[l]), 0.f)), l == D - 1 ? INFINITY : a.qval[s0 + pos]);
-      }
+      zw_write_row(a.ZW, a.zw_nq, a.KT, qi, r, D,
+                   [&](int l) { return sqrtf(fmaxf(w_unpack(keys[l]), 0.f)); },
+                   [&](int l) { return l == D - 1 ? INFINITY : a.qval[s0 + (uint32_t)keys[l]]; });
     }
   } else {
     const int64_t o0 = flat * (int64_t)a.k;

@@ -8,9 +8,10 @@
 //
 // Layout and mapping: a wave owns one database row at a time; its lanes
 // stride over the row's non-zeros (coalesced 8-byte (word, weight) loads),
-// apply QB queries' tables to each non-zero, then reduce across the wave
-// with a fixed butterfly.  The per-row sum therefore has a fixed order that
-// does not depend on which other queries or rows share the launch.
+// apply a group of kQB queries' tables to each non-zero, then reduce across
+// the wave with a fixed butterfly.  The per-row sum therefore has a fixed
+// order that does not depend on which other queries or rows share the
+// launch.
 #include <algorithm>
 #include <climits>
 #include <mutex>
@@ -20,9 +21,7 @@
 
 namespace lcemd {
 
-constexpr int kDocsPerWave = 4;
-constexpr int kDocsPerWG = kDocsPerWave * (kThreads / 64);
-constexpr int kQB = 4;
+constexpr int kQB = 16;  // queries per work item (one contiguous table run per non-zero)
 constexpr int kItemDocs = 16;  // database rows per work item of the persistent kernel
 
 __device__ __forceinline__ float wave_sum(float t) {
@@ -42,17 +41,16 @@ __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
   acc = fmaf(r, z, acc);
 }
 
-// Costs of database row u against queries q0 .. q0+nqb-1 (one wave).
-// EVEN: the table stride is even, so every row starts 16-byte aligned and
-// the first two entries of all QB queries are fetched as independent
-// 16-byte loads before any of them is consumed (the walk along a row is a
-// chain of dependent loads otherwise).  Entries past a row's sink are read
-// but never used: the sink leaves no mass.
-template <bool EVEN>
+// Costs of database row u against queries q0 .. q0+nqb-1 (one wave).  For
+// a non-zero of word r, the first pair of table entries of the kQB queries
+// is one contiguous run (see zw_at); the kQB 16-byte loads are all issued
+// before any is consumed (the walk along a row is a chain of dependent
+// loads otherwise).  Entries past a row's sink are never used: the sink
+// leaves no mass.
 __device__ __forceinline__ void doc_costs(int lane, int64_t u, int64_t q0, int nqb,
                                           const int64_t* __restrict__ xptr,
                                           const int2* __restrict__ xcv,
-                                          const float2* __restrict__ ZW, int64_t v_used, int KT,
+                                          const float4* __restrict__ ZP, int64_t zw_nq, int KP,
                                           float* __restrict__ out, int64_t ld) {
   const int64_t e0 = xptr[u], e1 = xptr[u + 1];
   float t[kQB];
@@ -61,46 +59,39 @@ __device__ __forceinline__ void doc_costs(int lane, int64_t u, int64_t q0, int n
   for (int64_t e = e0 + lane; e < e1; e += 64) {
     const int2 cv = xcv[e];
     const float x = __int_as_float(cv.y);
-    const float2* row[kQB];
+    const float4* base = ZP + (int64_t)cv.x * KP * zw_nq + q0;
+    float4 f[kQB];
 #pragma unroll
-    for (int q = 0; q < kQB; ++q) row[q] = ZW + ((q0 + min(q, nqb - 1)) * v_used + cv.x) * (int64_t)KT;
-    if constexpr (EVEN) {
-      float4 f[kQB];
+    for (int q = 0; q < kQB; ++q) f[q] = base[min(q, nqb - 1)];
+    // walk all queries one pair of entries at a time, so the loads of a
+    // further pair for every query that still has mass go out together
+    float rem[kQB], acc[kQB];
+    bool any = false;
 #pragma unroll
-      for (int q = 0; q < kQB; ++q) f[q] = *(const float4*)row[q];
+    for (int q = 0; q < kQB; ++q) {
+      rem[q] = x;
+      acc[q] = 0.f;
+      step(rem[q], acc[q], f[q].x, f[q].y);
+      if (rem[q] > 0.f) step(rem[q], acc[q], f[q].z, f[q].w);
+      any = any || (q < nqb && rem[q] > 0.f);
+    }
+    for (int p = 1; any && p < KP; ++p) {
 #pragma unroll
-      for (int q = 0; q < kQB; ++q) {
-        if (q < nqb) {
-          float rem = x, acc = 0.f;
-          step(rem, acc, f[q].x, f[q].y);
-          if (rem > 0.f) {
-            step(rem, acc, f[q].z, f[q].w);
-            for (int l = 2; rem > 0.f && l < KT; l += 2) {
-              const float4 g = *(const float4*)(row[q] + l);
-              step(rem, acc, g.x, g.y);
-              if (rem > 0.f) step(rem, acc, g.z, g.w);
-            }
-          }
-          t[q] += acc;
-        }
-      }
-    } else {
-      float2 f[kQB];
-#pragma unroll
-      for (int q = 0; q < kQB; ++q) f[q] = row[q][0];
+      for (int q = 0; q < kQB; ++q)
+        if (q < nqb && rem[q] > 0.f) f[q] = base[p * zw_nq + q];
+      any = false;
 #pragma unroll
       for (int q = 0; q < kQB; ++q) {
-        if (q < nqb) {
-          float rem = x, acc = 0.f;
-          step(rem, acc, f[q].x, f[q].y);
-          for (int l = 1; rem > 0.f && l < KT; ++l) {
-            const float2 g = row[q][l];
-            step(rem, acc, g.x, g.y);
-          }
-          t[q] += acc;
+        if (q < nqb && rem[q] > 0.f) {
+          step(rem[q], acc[q], f[q].x, f[q].y);
+          if (rem[q] > 0.f) step(rem[q], acc[q], f[q].z, f[q].w);
+          any = any || rem[q] > 0.f;
         }
       }
     }
+#pragma unroll
+    for (int q = 0; q < kQB; ++q)
+      if (q < nqb) t[q] += acc[q];
   }
 #pragma unroll
   for (int q = 0; q < kQB; ++q) {
@@ -109,77 +100,35 @@ __device__ __forceinline__ void doc_costs(int lane, int64_t u, int64_t q0, int n
   }
 }
 
-template <bool EVEN>
-__global__ __launch_bounds__(kThreads) void k_phase2(const int64_t* __restrict__ xptr,
-                                                     const int2* __restrict__ xcv, int64_t n,
-                                                     const float2* __restrict__ ZW, int64_t v_used,
-                                                     int KT, int64_t nq, float* __restrict__ out,
-                                                     int64_t ld) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // XCD-aware order: workgroup i runs on XCD i % 8; each XCD walks a
-  // contiguous range of (query group, document chunk) tiles, documents
-  // fastest, so the hot rows of its queries' tables stay in its L2.
-  const int64_t nchunks = (n + kDocsPerWG - 1) / kDocsPerWG;
-  const int64_t total = (nq + kQB - 1) / kQB * nchunks;
-  const int64_t per = (int64_t)gridDim.x / 8;
-  const int64_t work = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (work >= total) return;
-  const int64_t q0 = (work / nchunks) * kQB;
-  const int nqb = (int)min((int64_t)kQB, nq - q0);
-  const int64_t ubase = (work % nchunks) * kDocsPerWG + wave * kDocsPerWave;
-  for (int j = 0; j < kDocsPerWave; ++j) {
-    const int64_t u = ubase + j;
-    if (u >= n) break;
-    doc_costs<EVEN>(lane, u, q0, nqb, xptr, xcv, ZW, v_used, KT, out, ld);
-  }
-}
-
-hipError_t launch_phase2(const int64_t* xptr, const int2* xcv, int64_t n, const float2* ZW,
-                         int64_t v_used, int KT, int64_t nq, float* out, int64_t ld,
-                         hipStream_t s) {
-  if (n <= 0 || nq <= 0) return hipSuccess;
-  const int64_t total = (nq + kQB - 1) / kQB * ((n + kDocsPerWG - 1) / kDocsPerWG);
-  const int64_t blocks = (total + 7) / 8 * 8;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (KT % 2 == 0)
-    hipLaunchKernelGGL(k_phase2<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, xptr, xcv, n,
-                       ZW, v_used, KT, nq, out, ld);
-  else
-    hipLaunchKernelGGL(k_phase2<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, xptr, xcv, n,
-                       ZW, v_used, KT, nq, out, ld);
-  return hipGetLastError();
-}
-
 // Persistent variant: a grid of resident workgroups whose waves pull
 // (query group, kItemDocs database rows) items from eight work counters, one per
 // XCD, each counter walking a contiguous eighth of the items (so an XCD
 // keeps a few queries' tables hot in its L2).  For fixed-shape batches the
 // live query count is read from device memory.  Every wave exits once its
 // counter passes the end of its range.
-template <bool EVEN>
 __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
     const int64_t* __restrict__ xptr, const int2* __restrict__ xcv, int64_t n,
-    const float2* __restrict__ ZW, int64_t v_used, int KT, int64_t nq_arg,
+    const float4* __restrict__ ZP, int64_t zw_nq, int KP, int64_t nq_arg,
     const int* __restrict__ nq_dev, float* __restrict__ out, int64_t ld,
     unsigned long long* __restrict__ counters) {
   const int lane = threadIdx.x & 63;
   const int xcd = blockIdx.x & 7;
   const int64_t nq = nq_dev ? (int64_t)*nq_dev : nq_arg;
-  const int64_t nd4 = (n + kItemDocs - 1) / kItemDocs;
-  const int64_t total = (nq + kQB - 1) / kQB * nd4;
+  const int64_t nd = (n + kItemDocs - 1) / kItemDocs;
+  const int64_t total = (nq + kQB - 1) / kQB * nd;
   const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
   while (true) {
     unsigned long long it = 0;
     if (lane == 0) it = atomicAdd(&counters[xcd], 1ull);
     const int64_t item = lo + (int64_t)__shfl((long long)it, 0);
     if (item >= hi) break;
-    const int64_t q0 = (item / nd4) * kQB;
+    const int64_t q0 = (item / nd) * kQB;
     const int nqb = (int)min((int64_t)kQB, nq - q0);
-    const int64_t ubase = (item % nd4) * kItemDocs;
+    const int64_t ubase = (item % nd) * kItemDocs;
     for (int j = 0; j < kItemDocs; ++j) {
       const int64_t u = ubase + j;
       if (u >= n) break;
-      doc_costs<EVEN>(lane, u, q0, nqb, xptr, xcv, ZW, v_used, KT, out, ld);
+      doc_costs(lane, u, q0, nqb, xptr, xcv, ZP, zw_nq, KP, out, ld);
     }
   }
 }
@@ -229,23 +178,18 @@ int persistent_grid(const void* fn, int threads, size_t shmem, int64_t items) {
 }
 
 hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n,
-                                    const float2* ZW, int64_t v_used, int KT, int64_t nq,
+                                    const float2* ZW, int64_t zw_nq, int KT, int64_t nq,
                                     const int* nq_dev, float* out, int64_t ld,
                                     unsigned long long* counters, hipStream_t s) {
   if (n <= 0 || (!nq_dev && nq <= 0)) return hipSuccess;
   hipError_t e = launch_zero_ints((int*)counters, 16, s);
   if (e != hipSuccess) return e;
-  // items: bounded by the batch size the kernel can see
+  // items (one per wave) bound the grid when the batch size is known here
   const int64_t items = nq_dev ? INT64_MAX / 2 : (nq + kQB - 1) / kQB * ((n + kItemDocs - 1) / kItemDocs) * 64;
-  const void* fn = KT % 2 == 0 ? (const void*)k_phase2_persistent<true> : (const void*)k_phase2_persistent<false>;
-  const int grid = persistent_grid(fn, kThreads, 0, items);
+  const int grid = persistent_grid((const void*)k_phase2_persistent, kThreads, 0, items);
   if (grid <= 0) return hipErrorInvalidConfiguration;
-  if (KT % 2 == 0)
-    hipLaunchKernelGGL(k_phase2_persistent<true>, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n,
-                       ZW, v_used, KT, nq, nq_dev, out, ld, counters);
-  else
-    hipLaunchKernelGGL(k_phase2_persistent<false>, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n,
-                       ZW, v_used, KT, nq, nq_dev, out, ld, counters);
+  hipLaunchKernelGGL(k_phase2_persistent, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n,
+                     (const float4*)ZW, zw_nq, (int)zw_pairs(KT), nq, nq_dev, out, ld, counters);
   return hipGetLastError();
 }
 

@@ -182,6 +182,7 @@ int issue(lcemd_server* s, Lane& L) {
     a.nq = s->B;
     a.KT = s->KT;
     a.ZW = L.ZW;
+    a.zw_nq = s->B;
     a.overflow = L.ints + 8;
     a.work_ctr = L.ctr;
     if (s->prec != LCEMD_FP32) {
@@ -191,7 +192,7 @@ int issue(lcemd_server* s, Lane& L) {
     }
     if ((rc = p1_launch(c, a, P1_TABLE, s->prec, s->KT, LCEMD_MAX_HIST, LCEMD_MAX_HIST))) break;
     if (s->prec != LCEMD_FP32) HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, L.ZW, c->v_used, s->KT, s->B, L.nq,
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, L.ZW, s->B, s->KT, s->B, L.nq,
                                        L.d2q, c->n, L.ctr + 8, L.stream));
     HIPCHK(c, launch_select(L.d2q, c->n, c->n, s->B, s->cld, nullptr, -1, L.cand, L.seltmp, L.stream));
     P1Args p = a;
@@ -222,7 +223,7 @@ int setup_lane(lcemd_server* s, Lane& L) {
   if ((rc = dalloc(c, L.qptr, B + 1, "lane")) || (rc = dalloc(c, L.qcol, W, "lane")) ||
       (rc = dalloc(c, L.qval, W, "lane")) || (rc = dalloc(c, L.nq, 1, "lane")) ||
       (rc = dalloc(c, L.ints, 16, "lane")) || (rc = dalloc(c, L.ctr, 16, "lane")) || (rc = dalloc(c, L.fixl, kFixCapLane, "lane")) ||
-      (rc = dalloc(c, L.ZW, B * c->v_used * s->KT, "lane tables")) ||
+      (rc = dalloc(c, L.ZW, B * c->v_used * 2 * zw_pairs(s->KT), "lane tables")) ||
       (rc = dalloc(c, L.d2q, B * n, "lane")) || (rc = dalloc(c, L.cand, B * s->cld, "lane")) ||
       (rc = dalloc(c, L.seltmp, select_tmp_elems(B, n, s->cld), "lane")) ||
       (rc = dalloc(c, L.q2dv, B * s->use, "lane")) ||
@@ -434,7 +435,7 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   // admission by device memory: lanes x slots x per-query state <= budget
   const int nlanes = cfg->use_graph ? 2 : 1;
   s->continuous = nlanes > 1;
-  const double per_q = (double)c->v_used * s->KT * 8 + (double)c->n * 4 + (double)s->cld * 8 +
+  const double per_q = (double)c->v_used * zw_pairs(s->KT) * 16 + (double)c->n * 4 + (double)s->cld * 8 +
                        (double)s->use * 4 * (1 + (LCEMD_MAX_HIST + kRows - 1) / kRows) + 64.0 * s->l;
   const int64_t budget = cfg->memory_budget > 0 ? cfg->memory_budget : (int64_t(4) << 30);
   const int64_t fit = (int64_t)(budget / (per_q * nlanes));
