@@ -324,15 +324,21 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     for (int i = 0; i < 4; ++i)
       a_nxt[i] = arow_ok ? *(const uint4*)(aptr + sl * 128 + i * 16) : make_uint4(0, 0, 0, 0);
   };
-  auto load_b = [&](int c0, int sl) {
+  // column operand: the 4 (column, 16-byte piece) addresses this thread
+  // stages are fixed for a pass; only the slice offset moves
+  const unsigned char* bptr[4];
+  auto set_b = [&](int c0) {
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int f = tid + it * kThreads;
-      const int c = f >> 3, q = f & 7;
-      const int cc = c0 + c;
-      b_nxt[it] = cc < h ? *(const uint4*)(base + (size_t)sm.cid[cc] * rowbytes + sl * 128 + q * 16)
-                         : make_uint4(0, 0, 0, 0);
+      const int cc = c0 + (f >> 3);
+      bptr[it] = cc < h ? base + (size_t)sm.cid[cc] * rowbytes + (f & 7) * 16 : nullptr;
     }
+  };
+  auto load_b = [&](int sl) {
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+      b_nxt[it] = bptr[it] ? *(const uint4*)(bptr[it] + sl * 128) : make_uint4(0, 0, 0, 0);
   };
 
   const int row = tid >> 1, sub = tid & 1;
@@ -341,7 +347,8 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
   int par = 0;
 
   load_a(0);
-  load_b(0, 0);
+  set_b(0);
+  load_b(0);
   for (int c0 = 0; c0 < h; c0 += kWC) {
     const int ntile = min(4, (h - c0 + 31) >> 5);
     floatx16 acc[4];
@@ -361,10 +368,11 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       __syncthreads();
       if (sl + 1 < nsl) {
         load_a(sl + 1);
-        load_b(c0, sl + 1);
+        load_b(sl + 1);
       } else if (c0 + kWC < h) {
         load_a(0);
-        load_b(c0 + kWC, 0);
+        set_b(c0 + kWC);
+        load_b(0);
       }
       slice_mfma<PREC>(ntile, acc, a_cur, sm.u.st, li, lh);
     }
@@ -387,11 +395,18 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
         }
       }
       __syncthreads();
+      // this thread's 32 contiguous columns, read without branches (the
+      // buffer is fully allocated; columns past h are masked afterwards)
       uint64_t kk[32];
+      const float2* krow = (const float2*)&sm.u.ck[row * kCK + 32 * sub];
 #pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        const int c = cb + sub + 2 * j;
-        kk[j] = (row_ok && c < h) ? w_pack(sm.u.ck[row * kCK + sub + 2 * j], (uint32_t)c) : ~0ull;
+      for (int j2 = 0; j2 < 16; ++j2) {
+        const float2 kv = krow[j2];
+        const int c = cb + 32 * sub + 2 * j2;
+        const uint64_t m0 = (row_ok && c < h) ? 0ull : ~0ull;
+        const uint64_t m1 = (row_ok && c + 1 < h) ? 0ull : ~0ull;
+        kk[2 * j2] = w_pack(kv.x, (uint32_t)c) | m0;
+        kk[2 * j2 + 1] = w_pack(kv.y, (uint32_t)(c + 1)) | m1;
       }
       const uint64_t* cur = &sm.lst[par][row * (KL + 1)];
       uint64_t* nxt = &sm.lst[par ^ 1][row * (KL + 1)];
