@@ -54,6 +54,39 @@ def parse():
     return ap.parse_args()
 
 
+def phase1_kernel(method, k, precision):
+    """The phase-1 kernel the library picks for the table (D2Q) pass."""
+    depth = {"rwmd": 1, "omr": 2, "act": k, "ict": 64}[method]
+    margin = 0 if precision == "fp32" or depth + 8 > 32 else 8
+    kl = 2
+    while kl < depth + margin:
+        kl *= 2
+    prec = 0 if margin == 0 else 1
+    if depth + margin <= 32:
+        return f"k_phase1_wide<0, {kl}, {prec}>"
+    return "k_phase1_fast<0, 64, 0>" if depth <= 64 else "k_phase1_f32"
+
+
+def measured_traffic(kernel, a):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary of this workload, if it was taken on the current kernel source
+    (its sha256 is recorded with it); otherwise None."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1812_02091_amd", "csrc", "phase1_wide.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    key = f"{a.workload}:{a.method}:{a.k}:{a.direction}:{a.precision}"
+    e = rec.get(key)
+    if not e or e.get("source_sha256") != digest or e.get("kernel") != kernel:
+        return None
+    return e["bytes_per_launch"]
+
+
 def copy_calibration():
     """A plain device-to-device copy of known size: its FETCH_SIZE and
     WRITE_SIZE counters convert the counters of the real kernels to bytes."""
@@ -237,9 +270,10 @@ def main():
     per_launch_flops = p1["work"] / max(1, p1["launches"])
     achieved = per_launch_flops / (per_launch_ms * 1e-3) if per_launch_ms > 0 else 0.0
     peak = PEAKS.get(a.precision, PEAKS["fp32"])
+    kernel = phase1_kernel(a.method, a.k, a.precision)
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": "k_phase1_fast (table mode)",
+                "frac": achieved / peak, "traffic": measured_traffic(kernel, a),
+                "kernel": kernel,
                 "avg_launch_ms": per_launch_ms,
                 "flops_per_launch": per_launch_flops}
     p2 = phases.get("phase2")
