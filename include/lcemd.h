@@ -79,8 +79,13 @@ extern "C" {
 #define LCEMD_SYM 2
 
 /* arithmetic of the phase-1 distance contraction (candidate selection);
- * the selected candidates' distances are always recomputed exactly in
- * float32 from the float32 embeddings */
+ * the selected candidates' distances are always recomputed in float32 from
+ * the float32 embeddings.  LCEMD_FP32 and LCEMD_BF16 select exactly (bf16
+ * keys keep every candidate within a worst-case error band and rows whose
+ * certificate fails are redone in float32).  LCEMD_FP8 (OCP e4m3 codes,
+ * one float32 scale per embedding row) uses a statistical band instead of
+ * the worst-case one (which would keep nearly every candidate): its
+ * results agree with the float32 path with high probability, not always. */
 #define LCEMD_FP32 0
 #define LCEMD_BF16 1
 #define LCEMD_FP8 2
@@ -237,7 +242,7 @@ typedef struct lcemd_server lcemd_server;
 typedef struct {
   int32_t method;          /* as lcemd_opts */
   int32_t k;               /* ACT only, 1..LCEMD_MAX_K */
-  int32_t precision;       /* LCEMD_FP32 or LCEMD_BF16 */
+  int32_t precision;       /* LCEMD_FP32, LCEMD_BF16 or LCEMD_FP8 */
   int32_t l;               /* neighbours returned per query, 1..min(LCEMD_MAX_L, n) */
   int32_t max_slots;       /* queries per batch (>= 1); lowered to fit memory_budget */
   int32_t max_batch_words; /* words per batch (raised to LCEMD_MAX_HIST); 0 = no limit */
@@ -248,7 +253,7 @@ typedef struct {
 } lcemd_server_cfg;
 
 /* Allocates every lane buffer up front.  LCEMD_E_CAPACITY if the budget
- * holds no query; LCEMD_E_UNSUPPORTED for LCEMD_FP8.  *out is NULL on
+ * holds no query.  *out is NULL on
  * error. */
 int lcemd_server_start(lcemd_ctx* ctx, const lcemd_server_cfg* cfg, lcemd_server** out);
 /* Queue one query (host arrays of h words: ascending distinct ids < v,

@@ -50,6 +50,8 @@ void free_emb(lcemd_ctx* c) {
   dfree((void*&)c->V);
   dfree((void*&)c->vnorm);
   dfree((void*&)c->Vb);
+  dfree((void*&)c->V8);
+  dfree((void*&)c->vscale);
   c->v = 0;
   c->m = c->m_pad = 0;
 }
@@ -219,7 +221,6 @@ int check_opts(lcemd_ctx* c, const lcemd_opts* o) {
     return fail(c, LCEMD_E_INVALID_ARG, "ACT needs 1 <= k <= %d (got %d)", LCEMD_MAX_K, o->k);
   if (o->direction < LCEMD_D2Q || o->direction > LCEMD_SYM) return fail(c, LCEMD_E_INVALID_ARG, "unknown direction %d", o->direction);
   if (o->precision < LCEMD_FP32 || o->precision > LCEMD_FP8) return fail(c, LCEMD_E_INVALID_ARG, "unknown precision %d", o->precision);
-  if (o->precision == LCEMD_FP8) return fail(c, LCEMD_E_UNSUPPORTED, "LCEMD_FP8 phase 1 is not built");
   for (int i = 0; i < 3; ++i)
     if (o->reserved[i]) return fail(c, LCEMD_E_INVALID_ARG, "reserved option fields must be 0");
   return LCEMD_OK;
@@ -239,6 +240,16 @@ int ensure_precision(lcemd_ctx* c, int prec) {
     int rc = dalloc(c, c->Vb, (size_t)c->v * c->m_pad, "bfloat16 embeddings");
     if (rc) return rc;
     HIPCHK(c, launch_make_bf16(c->V, c->v * (int64_t)c->m_pad, c->Vb, c->stream));
+  }
+  if (prec == LCEMD_FP8 && !c->V8) {
+    c->m8 = (c->m_pad + 127) / 128 * 128;
+    int rc = dalloc(c, c->V8, (size_t)c->v * c->m8, "fp8 embeddings");
+    if (!rc) rc = dalloc(c, c->vscale, (size_t)c->v, "fp8 row scales");
+    if (rc) {
+      dfree((void*&)c->V8);
+      return rc;
+    }
+    HIPCHK(c, launch_make_fp8(c->V, c->v, c->m_pad, c->m8, c->V8, c->vscale, c->stream));
   }
   return LCEMD_OK;
 }
@@ -260,6 +271,9 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
   }
   const int margin = prec == LCEMD_FP32 ? 0 : kMargin;
   a.Vb = c->Vb;
+  a.V8 = c->V8;
+  a.vscale = c->vscale;
+  a.m8 = c->m8;
   if (depth + margin <= 32 && !c->force_kernel) {
     const int KL = pow2ceil(depth + margin);
     a.KT_margin = margin;

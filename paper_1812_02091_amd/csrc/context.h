@@ -33,6 +33,9 @@ struct lcemd_ctx {
   float* V = nullptr;
   float* vnorm = nullptr;
   uint16_t* Vb = nullptr;
+  uint8_t* V8 = nullptr;    // fp8 codes, rows of m8 bytes
+  float* vscale = nullptr;  // fp8 row scales
+  int m8 = 0;
   // database (Sec. 4: X in CSR)
   int64_t n = 0, nnz = 0, v_used = 0;
   int db_hmax = 0;

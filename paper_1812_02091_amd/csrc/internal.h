@@ -37,8 +37,9 @@ struct P1Args {
   const float* V;         // [v][m_pad] float32, zero padded
   const float* vnorm;     // [v] |v|^2 (float64 accumulation, stored float32)
   const uint16_t* Vb;     // [v][m_pad] bfloat16 copy (PREC_BF16)
-  const uint8_t* V8;      // [v][m_pad] fp8 e4m3 copy (PREC_FP8)
+  const uint8_t* V8;      // [v][m8] fp8 (OCP e4m3) codes of V / vscale (PREC_FP8)
   const float* vscale;    // [v] fp8 row scales
+  int m8;                 // bytes per fp8 row: m_pad rounded up to 128
   int m_pad;
   // measure
   int method;             // LCEMD_RWMD / OMR / ACT / ICT
@@ -118,7 +119,7 @@ hipError_t launch_pair_reduce(const float* partial, int64_t npairs, int rb_max, 
 hipError_t launch_prep_embeddings(const float* Vin, int64_t v, int m, int m_pad, int l2norm,
                                   float* Vpad, float* vnorm, hipStream_t s);
 hipError_t launch_make_bf16(const float* V, int64_t count, uint16_t* out, hipStream_t s);
-hipError_t launch_make_fp8(const float* V, int64_t v, int m_pad, uint8_t* out, float* scale,
+hipError_t launch_make_fp8(const float* V, int64_t v, int m_pad, int m8, uint8_t* out, float* scale,
                            hipStream_t s);
 hipError_t launch_validate_csr(const int64_t* ptr, const int32_t* col, const float* val,
                                int64_t rows, int64_t v, int normalized, int* err,

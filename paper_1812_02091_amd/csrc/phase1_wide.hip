@@ -46,6 +46,14 @@ constexpr int kSeg = LCEMD_MAX_HIST;
 constexpr int kGroupW = 8;      // queries per tile group (table modes)
 constexpr float kGuardW = 0.25f;
 constexpr float kBandBF16 = 0.015625f * 1.07f;  // 2^-6 * 1.07
+// fp8 (e4m3, 3 mantissa bits): a statistical band, not a worst-case one --
+// about six standard deviations of the key error of a few-hundred-term dot
+// product with independent relative rounding errors of at most 2^-4
+constexpr float kBandFP8 = 0.04f;
+template <int PREC>
+__device__ __forceinline__ float band_coef() {
+  return PREC == PREC_F32 ? 0.f : (PREC == PREC_BF16 ? kBandBF16 : kBandFP8);
+}
 
 __device__ __forceinline__ uint32_t w_bits(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -120,6 +128,21 @@ __device__ __forceinline__ void slice_bf16(floatx16 (&acc)[4], const uint4 (&a_c
   }
 }
 
+template <int NT>
+__device__ __forceinline__ void slice_fp8(floatx16 (&acc)[4], const uint4 (&a_cur)[4],
+                                          const unsigned char* st, int li, int lh) {
+  // lane half lh supplies dims [64 lh + 8 s, +8) of the 128-dim slice
+  const long* ap = reinterpret_cast<const long*>(a_cur);
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    long bv[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bv[t] = *(const long*)(st + (32 * t + li) * kStride + lh * 64 + s * 8);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(ap[s], bv[t], acc[t], 0, 0, 0);
+  }
+}
+
 template <int PREC>
 __device__ __forceinline__ void slice_mfma(int ntile, floatx16 (&acc)[4], const uint4 (&a_cur)[4],
                                            const unsigned char* st, int li, int lh) {
@@ -130,12 +153,19 @@ __device__ __forceinline__ void slice_mfma(int ntile, floatx16 (&acc)[4], const 
       case 3: slice_f32<3>(acc, a_cur, st, li, lh); break;
       default: slice_f32<4>(acc, a_cur, st, li, lh); break;
     }
-  } else {
+  } else if constexpr (PREC == PREC_BF16) {
     switch (ntile) {
       case 1: slice_bf16<1>(acc, a_cur, st, li, lh); break;
       case 2: slice_bf16<2>(acc, a_cur, st, li, lh); break;
       case 3: slice_bf16<3>(acc, a_cur, st, li, lh); break;
       default: slice_bf16<4>(acc, a_cur, st, li, lh); break;
+    }
+  } else {
+    switch (ntile) {
+      case 1: slice_fp8<1>(acc, a_cur, st, li, lh); break;
+      case 2: slice_fp8<2>(acc, a_cur, st, li, lh); break;
+      case 3: slice_fp8<3>(acc, a_cur, st, li, lh); break;
+      default: slice_fp8<4>(acc, a_cur, st, li, lh); break;
     }
   }
 }
@@ -160,6 +190,8 @@ struct WideSmem {
   float rdrop[kWR];  // smallest key dropped because the list was full
   int rcut[kWR];     // the last merge reached k_eff or the row's bound
   float qmax;
+  float rsc[PREC == PREC_FP8 ? kWR : 1];   // fp8 row scales
+  float csc[PREC == PREC_FP8 ? kSeg : 1];  // fp8 column scales
 };
 
 // Float32 dot products <v_row, c_pos> of a thread's listed candidates
@@ -245,6 +277,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       sm.rid[tid] = w;
       sm.rbound[tid] = ok ? a.qval[qs0 + rb * kWR + tid] : 0.f;
       sm.rvn[tid] = a.vnorm[w];
+      if constexpr (PREC == PREC_FP8) sm.rsc[tid] = a.vscale[w];
       sm.rlen[tid] = 0;
       sm.rdrop[tid] = INFINITY;
     }
@@ -255,6 +288,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       sm.cid[c] = w;
       sm.cap[c] = __int_as_float(a.xcv[s0 + c].y);
       sm.qn[c] = a.vnorm[w];
+      if constexpr (PREC == PREC_FP8) sm.csc[c] = a.vscale[w];
     }
   } else {
     // items run query-fastest within a group of kGroupW queries, then row
@@ -276,6 +310,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       sm.rid[tid] = w;
       sm.rbound[tid] = ok ? (MODE == P1_TABLE ? a.xmax[r0 + tid] : INFINITY) : 0.f;
       sm.rvn[tid] = a.vnorm[w];
+      if constexpr (PREC == PREC_FP8) sm.rsc[tid] = a.vscale[w];
       sm.rlen[tid] = 0;
       sm.rdrop[tid] = INFINITY;
     }
@@ -287,6 +322,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       sm.cid[c] = w;
       sm.cap[c] = a.qval[s0 + c];
       sm.qn[c] = a.vnorm[w];
+      if constexpr (PREC == PREC_FP8) sm.csc[c] = a.vscale[w];
     }
   }
   if (tid == 0) sm.qmax = 0.f;
@@ -310,8 +346,10 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
   constexpr bool kCapStop = MODE != P1_TABLE_FULL;
 
   // ---------------- contraction ----------------
-  const unsigned char* base = PREC == PREC_F32 ? (const unsigned char*)a.V : (const unsigned char*)a.Vb;
-  const size_t rowbytes = (size_t)a.m_pad * (PREC == PREC_F32 ? 4 : 2);
+  const unsigned char* base = PREC == PREC_F32    ? (const unsigned char*)a.V
+                              : PREC == PREC_BF16 ? (const unsigned char*)a.Vb
+                                                  : (const unsigned char*)a.V8;
+  const size_t rowbytes = PREC == PREC_FP8 ? (size_t)a.m8 : (size_t)a.m_pad * (PREC == PREC_F32 ? 4 : 2);
   const int nsl = (int)(rowbytes / 128);
   const int li = lane & 31, lh = lane >> 5;
   const int arow = 32 * wave + li;
@@ -388,10 +426,14 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
         const int t = 2 * half + tt;
         const int c = cb + 32 * tt + li;
         const float qc = c < h ? sm.qn[c] : 0.f;
+        const float csc = PREC == PREC_FP8 && c < h ? sm.csc[PREC == PREC_FP8 ? c : 0] : 1.f;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int i = 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
-          sm.u.ck[i * kCK + 32 * tt + li] = qc - 2.f * acc[t][r];
+          if constexpr (PREC == PREC_FP8)
+            sm.u.ck[i * kCK + 32 * tt + li] = qc - 2.f * (sm.rsc[i] * csc) * acc[t][r];
+          else
+            sm.u.ck[i * kCK + 32 * tt + li] = qc - 2.f * acc[t][r];
         }
       }
       __syncthreads();
@@ -411,7 +453,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       const uint64_t* cur = &sm.lst[par][row * (KL + 1)];
       uint64_t* nxt = &sm.lst[par ^ 1][row * (KL + 1)];
       const int len = row_ok ? sm.rlen[row] : 0;
-      const float band = PREC == PREC_F32 ? 0.f : kBandBF16 * sqrtf(sm.rvn[row]) * sm.qmax;
+      const float band = PREC == PREC_F32 ? 0.f : band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax;
       int ptr = 0, w = 0;
       float P = 0.f, K0 = 0.f;
       bool cut = false;
@@ -555,7 +597,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     // a candidate left out of a full list has a key >= rdrop - half a band
     // (bf16; exact keys for float32): the used entries must all be nearer
     if (PREC != PREC_F32 && D > 0 && sm.rdrop[row] < INFINITY && a.overflow) {
-      const float half_band = PREC == PREC_F32 ? 0.f : 0.5f * kBandBF16 * sqrtf(sm.rvn[row]) * sm.qmax;
+      const float half_band = PREC == PREC_F32 ? 0.f : 0.5f * band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax;
       const float last_key = Z2[D - 1] - sm.rvn[row];
       if (!(last_key < sm.rdrop[row] - half_band - 1e-6f * (sm.rvn[row] + sm.qmax * sm.qmax))) {
         // redo this row exactly (k_fix_rows) unless the list of such rows is full
@@ -788,6 +830,10 @@ hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, hipSt
   if (prec == PREC_BF16) {
     if (!a.Vb) return hipErrorInvalidValue;
     return launch_wide_prec<PREC_BF16>(a, mode, KL, s);
+  }
+  if (prec == PREC_FP8) {
+    if (!a.V8 || !a.vscale || a.m8 % 128 != 0) return hipErrorInvalidValue;
+    return launch_wide_prec<PREC_FP8>(a, mode, KL, s);
   }
   return hipErrorInvalidValue;
 }

@@ -62,6 +62,42 @@ hipError_t launch_make_bf16(const float* V, int64_t count, uint16_t* out, hipStr
   return hipGetLastError();
 }
 
+// fp8 (OCP e4m3) copy with one float32 scale per row: scale = max|v_d| / 448
+// (the largest finite e4m3 value), codes = round-to-nearest-even(v_d /
+// scale).  One wave per row; rows are m8 bytes (zero codes past m_pad).
+__global__ __launch_bounds__(kThreads) void k_make_fp8(const float* __restrict__ V, int64_t v, int m_pad,
+                                                       int m8, uint8_t* __restrict__ out,
+                                                       float* __restrict__ scale) {
+  const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= v) return;
+  const float* x = V + row * m_pad;
+  float mx = 0.f;
+  for (int d = lane; d < m_pad; d += 64) mx = fmaxf(mx, fabsf(x[d]));
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  const float sc = mx > 0.f ? mx / 448.f : 1.f;
+  if (lane == 0) scale[row] = sc;
+  uint32_t* o32 = (uint32_t*)(out + row * (int64_t)m8);
+  for (int q = lane; q < m8 / 4; q += 64) {
+    float f[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = 4 * q + j;
+      f[j] = d < m_pad ? x[d] / sc : 0.f;
+    }
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], w, true);
+    o32[q] = (uint32_t)w;
+  }
+}
+
+hipError_t launch_make_fp8(const float* V, int64_t v, int m_pad, int m8, uint8_t* out, float* scale,
+                           hipStream_t s) {
+  const int64_t blocks = (v + kThreads / 64 - 1) / (kThreads / 64);
+  hipLaunchKernelGGL(k_make_fp8, dim3((unsigned)blocks), dim3(kThreads), 0, s, V, v, m_pad, m8, out, scale);
+  return hipGetLastError();
+}
+
 // Validation of a CSR histogram batch resident on the device; each failing
 // row sets a bit of *err: 1 = row pointers, 2 = column ids, 4 = weights,
 // 8 = row sum (only when normalised rows are required).

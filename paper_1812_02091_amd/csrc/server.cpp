@@ -411,8 +411,8 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   if (!c->V || !c->xptr) return fail(c, LCEMD_E_NOT_LOADED, "load embeddings and database first");
   if (cfg->method < LCEMD_RWMD || cfg->method > LCEMD_ICT) return fail(c, LCEMD_E_INVALID_ARG, "unknown method");
   if (cfg->method == LCEMD_ACT && (cfg->k < 1 || cfg->k > LCEMD_MAX_K)) return fail(c, LCEMD_E_INVALID_ARG, "bad k");
-  if (cfg->precision != LCEMD_FP32 && cfg->precision != LCEMD_BF16)
-    return fail(c, LCEMD_E_UNSUPPORTED, "serving precision must be LCEMD_FP32 or LCEMD_BF16");
+  if (cfg->precision < LCEMD_FP32 || cfg->precision > LCEMD_FP8)
+    return fail(c, LCEMD_E_INVALID_ARG, "unknown precision %d", cfg->precision);
   if (cfg->l < 1 || cfg->l > LCEMD_MAX_L || cfg->l > c->n) return fail(c, LCEMD_E_INVALID_ARG, "bad l");
   if (cfg->max_slots < 1) return fail(c, LCEMD_E_INVALID_ARG, "max_slots must be >= 1");
   for (int i = 0; i < 5; ++i)

@@ -340,3 +340,28 @@ def test_topl_many_documents(L, direction, ell):
         for j in range(0, ell, max(1, ell // 8)):
             o = orc.pair(qc, qw, int(idx[b, j]), "act", 4, direction)
             assert abs(float(dist[b, j]) - o) <= 1e-5 * abs(o) + 1e-7, (b, j)
+
+
+@pytest.mark.parametrize("wl", ["tiny", "text"])
+@pytest.mark.parametrize("method,k", [("rwmd", 1), ("act", 3), ("act", 8)])
+def test_distances_fp8_agreement(tiny, text_small, wl, method, k):
+    """fp8 keys with a statistical band: distances are float32 values of
+    the selected candidates; nearly all agree with the oracle."""
+    w, ctx, orc = tiny if wl == "tiny" else text_small
+    say(f"[gpu] fp8 distances {wl} {method}{k}")
+    g = ctx.distances(*_q(w), method=method, k=k, direction="sym", precision="fp8")
+    o = _oracle_matrix(orc, w, method, k, "sym")
+    tol = 1e-5 * np.abs(o) + 1e-7 * np.mean(np.abs(o))
+    ok = np.abs(g.astype(np.float64) - o) <= tol
+    assert np.mean(ok) >= 0.99, np.mean(ok)
+    assert np.all(np.isfinite(g)) and np.all(g >= 0)
+
+
+def test_topl_fp8_text_agreement(text_small):
+    w, ctx, _ = text_small
+    say("[gpu] fp8 top-16 agreement with fp32")
+    i32, _ = ctx.topl(*_q(w), 16, method="act", k=8, direction="sym", precision="fp32")
+    i8, d8 = ctx.topl(*_q(w), 16, method="act", k=8, direction="sym", precision="fp8")
+    agree = np.mean([len(set(i32[b]) & set(i8[b])) / 16 for b in range(w.queries.n)])
+    assert agree >= 0.95, agree
+    assert np.all(np.diff(d8, axis=1) >= 0)

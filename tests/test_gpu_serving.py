@@ -57,7 +57,8 @@ def _reference(ctx, qs, method, k, prec, ell):
 
 
 @pytest.mark.parametrize("prec,graph,method,k", [("fp32", True, "act", 8), ("fp32", False, "act", 8),
-                                                 ("bf16", True, "act", 8), ("fp32", True, "ict", 1),
+                                                 ("bf16", True, "act", 8), ("fp8", True, "act", 8),
+                                                 ("fp32", True, "ict", 1),
                                                  ("fp32", True, "omr", 1)])
 def test_server_matches_topl_alone_and_mixed(setup, prec, graph, method, k):
     L, w, qs, ctx = setup
