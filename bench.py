@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=2, help="queries in the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the bf16-path comparison")
+    ap.add_argument("--no-big", action="store_true", help="skip the 1M-word precision and serving section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--big-queries", type=int, default=4096, help="queries of the 1M-word precision run")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="offered load, queries/s")
     ap.add_argument("--serve-queries", type=int, default=1000)
     ap.add_argument("--serve-sat", type=int, default=256, help="queries in the saturation sample")
@@ -118,7 +120,7 @@ def _oracle_task(args):
     t0 = time.time()
     row = _ORC.row_distances(qc, qw, method, k, "sym")
     _ORC.top_l(row, ell)
-    return row.shape[0], time.time() - t0
+    return row.shape[0], time.time() - t0, row
 
 
 def cpu_baseline(w, method, k, ell, nq):
@@ -133,31 +135,101 @@ def cpu_baseline(w, method, k, ell, nq):
     pairs = sum(r[0] for r in res)
     # per-worker compute time (excludes process start-up); queries run in parallel
     dt = max(sum(r[1] for r in res) / cores, max(r[1] for r in res))
-    return {"value": pairs / dt, "unit": "distances/s", "cores": cores, "kind": "oracle",
-            "sample": f"{nq} queries x all {w.db.n} database rows, {method.upper()} k={k} symmetric "
-                      f"+ top-{ell}, float64 numpy/scipy, {cores} worker processes, {dt:.1f} s of oracle time per worker"}
+    rec = {"value": pairs / dt, "unit": "distances/s", "cores": cores, "kind": "oracle",
+           "sample": f"{nq} queries x all {w.db.n} database rows, {method.upper()} k={k} symmetric "
+                     f"+ top-{ell}, float64 numpy/scipy, {cores} worker processes, {dt:.1f} s of oracle time per worker"}
+    return rec, [r[2] for r in res]
 
 
-def serving_bench(a, lcemd):
-    """Serving on the 1M-word / 1M-document workload: a Poisson query stream
-    (open loop; 10-500 words per query) against the resident database, ACT
-    k=8, symmetric top-16.  Two paths: bf16 phase 1 on two graph-captured
-    lanes with continuous admission, and float32 phase 1 on one lane with
-    kernels launched per batch and a batch admitted only when the previous
-    one is done.  Latency = completion - scheduled arrival."""
+def oracle_error(ctx, w, nq, rows, method, k, precision):
+    """Relative error of the library's symmetric distances (first nq
+    queries, every database row) against the float64 oracle rows."""
+    import numpy as np
+
+    q = w.queries.take(list(range(nq)))
+    g = ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="sym", precision=precision)
+    o = np.stack(rows)
+    rel = np.abs(g.astype(np.float64) - o) / np.maximum(np.abs(o), 1e-30)
+    rel[o == 0] = np.where(g[o == 0] == 0, 0.0, np.inf)
+    return {"max_rel_err_vs_fp64_oracle": float(rel.max()), "median_rel_err_vs_fp64_oracle": float(np.median(rel)),
+            "pairs": int(rel.size)}
+
+
+def big_workload(a, lcemd):
+    """The 1M-word / 1M-document workload: (1) the precision variant -- one
+    symmetric ACT k=8 top-16 call over the whole query batch with float32,
+    bf16 and fp8 phase-1 keys: rates, top-16 agreement with float32, and the
+    error of returned distances against the float64 oracle on sampled
+    (query, neighbour) pairs; (2) serving (see serve_path)."""
+    import numpy as np
+
+    from synth import make_workload
+
+    t0 = time.time()
+    w = make_workload("text-1M", B=a.big_queries)
+    print(f"[bench] 1M-word workload built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
+    v, n, B = w.V.shape[0], w.db.n, w.queries.n
+    res = {"workload": f"text-1M: vocab {v} x {w.V.shape[1]}, {n} database histograms "
+                       f"({w.db.nnz} non-zeros), {B} queries, ACT k=8 symmetric, top-16"}
+    prec = {}
+    qs = w.queries
+    ref = None
+    rng = np.random.default_rng(77)
+    sample = [(int(b), int(j)) for b, j in zip(rng.integers(0, B, 24), rng.integers(0, 16, 24))]
+    small = qs.take(list(range(8)))
+    for p in ("fp32", "bf16", "fp8"):
+        ctx.topl(small.rowptr, small.col, small.val, 16, method="act", k=8, direction="sym", precision=p)
+        t1 = time.perf_counter()
+        idx, dist = ctx.topl(qs.rowptr, qs.col, qs.val, 16, method="act", k=8, direction="sym", precision=p)
+        dt = time.perf_counter() - t1
+        rec = {"distances_per_s": B * n / dt, "s_per_batch": dt}
+        if ref is None:
+            ref = (idx, dist)
+        else:
+            rec["top16_agreement_vs_fp32"] = float(np.mean([len(set(ref[0][i]) & set(idx[i])) / 16 for i in range(B)]))
+        rec["_pairs"] = [(b, int(idx[b, j]), float(dist[b, j])) for b, j in sample]
+        prec[p] = rec
+        print(f"[bench] 1M-word {p}: {dt:.2f} s", file=sys.stderr, flush=True)
+    # float64 oracle on the sampled (query, returned neighbour) pairs
+    from oracle import emd_oracle as O
+
+    docs = sorted({u for p in prec.values() for (_, u, _) in p["_pairs"]})
+    sub = w.db.take(docs)
+    pos = {u: i for i, u in enumerate(docs)}
+    orc = O.Oracle(w.V, sub.rowptr, sub.col, sub.val)
+    for p, rec in prec.items():
+        errs = []
+        for b, u, d in rec.pop("_pairs"):
+            qc, qw = qs.row(b)
+            o = orc.pair(qc, qw, pos[u], "act", 8, "sym")
+            errs.append(abs(d - o) / max(abs(o), 1e-30))
+        rec["max_rel_err_vs_fp64_oracle"] = float(np.max(errs))
+        rec["median_rel_err_vs_fp64_oracle"] = float(np.median(errs))
+        rec["oracle_pairs"] = len(errs)
+    res["precision"] = prec
+    fb, fixed = ctx.counters()
+    res["fallback_tiles"], res["rows_redone_exactly"] = fb, fixed
+    del w, qs, sub, orc
+    if not a.no_serving:
+        res["serving"] = serve_path(a, lcemd, ctx, v, n)
+    ctx.close()
+    return res
+
+
+def serve_path(a, lcemd, ctx, v, n):
+    """Serving on the resident 1M-word database: a Poisson query stream
+    (open loop; 10-500 words per query), ACT k=8, symmetric top-16.  Two
+    paths: bf16 phase 1 on two graph-captured lanes with continuous
+    admission, and float32 phase 1 on one lane with kernels launched per
+    batch and a batch admitted only when the previous one is done.
+    Latency = completion - scheduled arrival."""
     import threading
 
     import numpy as np
 
-    from synth import arrival_trace, make_workload
+    from synth import arrival_trace
 
-    t0 = time.time()
-    w = make_workload("text-1M", B=1)
-    print(f"[bench] serving workload built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
-    v = w.V.shape[0]
-    n = w.db.n
-    del w
     _, qs = arrival_trace(a.serve_rate, a.serve_queries + a.serve_sat, v, lmin=10, lmax=500)
     rows = [qs.row(b) for b in range(qs.n)]
     res = {}
@@ -205,12 +277,8 @@ def serving_bench(a, lcemd):
                      "saturation_qps": sat_qps,
                      "saturation_distances_per_s": sat_qps * n}
         print(f"[bench] serving {prec}: {res[prec]}", file=sys.stderr, flush=True)
-    fb, fixed = ctx.counters()
-    ctx.close()
-    res["workload"] = (f"text-1M: vocab {v} x 300, {n} database histograms resident; Poisson arrivals, "
-                       f"10-500 words per query, ACT k=8 symmetric top-16, up to {a.serve_slots} "
-                       f"queries per batch; saturation = {a.serve_sat} queries submitted at once")
-    res["bf16_rows_redone_exactly"] = fixed
+    res["setup"] = (f"Poisson arrivals at {a.serve_rate:g} qps, 10-500 words per query, up to "
+                    f"{a.serve_slots} queries per batch; saturation = {a.serve_sat} queries submitted at once")
     return res
 
 
@@ -285,39 +353,49 @@ def main():
         phase_report["phase2"]["algorithmic_GBps"] = p2_bytes / (p2_ms * 1e-3) / 1e9
         phase_report["phase2"]["hbm_frac"] = p2_bytes / (p2_ms * 1e-3) / HBM_PEAK
 
-    # the other phase-1 arithmetic on the same batch (bf16 keys vs float32 keys)
-    compare = None
-    if not a.no_compare:
-        other = "bf16" if a.precision == "fp32" else "fp32"
-        ref_idx = idx.cpu().numpy()
-        oi = torch.empty_like(idx)
-        od = torch.empty_like(dist)
-
-        def ostep():
-            ctx.topl(qp, qc, qv, a.ell, method=a.method, k=a.k, direction=a.direction,
-                     precision=other, out=(oi, od))
-
-        ostep()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(max(1, a.steps // 2)):
-            ostep()
-        torch.cuda.synchronize()
-        odt = (time.perf_counter() - t1) / max(1, a.steps // 2)
-        oidx = oi.cpu().numpy()
-        agree = float(np.mean([len(set(ref_idx[i]) & set(oidx[i])) / a.ell for i in range(B)]))
-        maxrel = float(np.max(np.abs(od.cpu().numpy().astype(np.float64) - dist.cpu().numpy())
-                              / np.maximum(dist.cpu().numpy().astype(np.float64), 1e-30)))
-        compare = {"precision": other, "value": B * n / odt, "ms_per_step": odt * 1e3,
-                   f"top{a.ell}_agreement_vs_{a.precision}": agree,
-                   "max_rel_diff_of_returned_distances": maxrel}
-
-    ctx.close()
-    serving = None if a.no_serving else serving_bench(a, lcemd)
-
-    cpu = None
+    cpu, orows = None, None
     if not a.no_cpu:
-        cpu = cpu_baseline(w, a.method, a.k, a.ell, min(a.cpu_queries, B))
+        cpu, orows = cpu_baseline(w, a.method, a.k, a.ell, min(a.cpu_queries, B))
+
+    # the other phase-1 arithmetics on the same batch, against this run's
+    # path (top-l agreement) and against the float64 oracle (sampled rows)
+    precisions = {}
+    if orows is not None:
+        precisions[a.precision] = oracle_error(ctx, w, len(orows), orows, a.method, a.k, a.precision)
+    if not a.no_compare:
+        ref_idx = idx.cpu().numpy()
+        ref_dist = dist.cpu().numpy().astype(np.float64)
+        for other in ("fp32", "bf16", "fp8"):
+            if other == a.precision:
+                continue
+            oi = torch.empty_like(idx)
+            od = torch.empty_like(dist)
+
+            def ostep():
+                ctx.topl(qp, qc, qv, a.ell, method=a.method, k=a.k, direction=a.direction,
+                         precision=other, out=(oi, od))
+
+            ostep()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(max(1, a.steps // 2)):
+                ostep()
+            torch.cuda.synchronize()
+            odt = (time.perf_counter() - t1) / max(1, a.steps // 2)
+            oidx = oi.cpu().numpy()
+            agree = float(np.mean([len(set(ref_idx[i]) & set(oidx[i])) / a.ell for i in range(B)]))
+            maxrel = float(np.max(np.abs(od.cpu().numpy().astype(np.float64) - ref_dist)
+                                  / np.maximum(ref_dist, 1e-30)))
+            rec = {"value": B * n / odt, "ms_per_step": odt * 1e3,
+                   f"top{a.ell}_agreement_vs_{a.precision}": agree,
+                   f"max_rel_diff_of_returned_distances_vs_{a.precision}": maxrel}
+            if orows is not None:
+                rec.update(oracle_error(ctx, w, len(orows), orows, a.method, a.k, other))
+            precisions[other] = rec
+    fb, fixed = ctx.counters()
+    counters = {"fallback_tiles": fb, "rows_redone_exactly": fixed}
+    ctx.close()
+    big = None if a.no_big else big_workload(a, lcemd)
 
     out = {
         "metric": "query-doc ACT distances/sec + p50/p99 query latency, BF16 vs FP32 path",
@@ -340,8 +418,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phase_report,
-        "other_precision": compare,
-        "serving": serving,
+        "precisions": precisions,
+        "counters": counters,
+        "text_1M": big,
     }
     print(json.dumps(out))
 

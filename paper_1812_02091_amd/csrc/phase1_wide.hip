@@ -73,6 +73,33 @@ __device__ __forceinline__ uint64_t w_shfl1(uint64_t v) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
 }
 
+// Selection keys.  float32 keys: (order-preserving key bits, position) in
+// 64 bits, exact order.  bf16/fp8 keys are approximate anyway (a band and an
+// exact re-sort follow), so they drop the key's 9 low bits for the position
+// (positions < 512): one 32-bit word, rounded down in value by at most
+// 2^-14 of the key's magnitude, which the band covers.
+template <int PREC>
+struct KeyOps {
+  using T = uint32_t;
+  static constexpr T kNone = 0xffffffffu;
+  __device__ static T pack(float f, uint32_t pos) { return (w_bits(f) & 0xfffffe00u) | pos; }
+  __device__ static float key(T k) {
+    const uint32_t o = k & 0xfffffe00u;
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+  }
+  __device__ static uint32_t pos(T k) { return k & 0x1ffu; }
+  __device__ static T shfl1(T v) { return (T)__shfl_xor((int)v, 1); }
+};
+template <>
+struct KeyOps<PREC_F32> {
+  using T = uint64_t;
+  static constexpr T kNone = ~0ull;
+  __device__ static T pack(float f, uint32_t pos) { return w_pack(f, pos); }
+  __device__ static float key(T k) { return w_unpack(k); }
+  __device__ static uint32_t pos(T k) { return (uint32_t)k; }
+  __device__ static T shfl1(T v) { return w_shfl1(v); }
+};
+
 __device__ __forceinline__ float w_exact_d2(const float* __restrict__ V, int m_pad, int a, int b) {
   const float4* x = (const float4*)(V + (size_t)a * m_pad);
   const float4* y = (const float4*)(V + (size_t)b * m_pad);
@@ -178,7 +205,7 @@ struct WideSmem {
     float qs[PREC == PREC_F32 ? 1 : kQSCap];  // segment vectors, a chunk of dims (exact recompute)
     float zb[kWR * (KL + 1)];         // exact squared distances of the lists
   } u;
-  uint64_t lst[2][kWR * (KL + 1)];  // row stride KL + 1 spreads rows over LDS banks
+  typename KeyOps<PREC>::T lst[2][kWR * (KL + 1)];  // row stride KL + 1 spreads rows over LDS banks
   int cid[kSeg];
   float cap[kSeg];
   float qn[kSeg];
@@ -439,57 +466,64 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       __syncthreads();
       // this thread's 32 contiguous columns, read without branches (the
       // buffer is fully allocated; columns past h are masked afterwards)
-      uint64_t kk[32];
+      using KO = KeyOps<PREC>;
+      using KT_ = typename KO::T;
+      KT_ kk[32];
       const float2* krow = (const float2*)&sm.u.ck[row * kCK + 32 * sub];
 #pragma unroll
       for (int j2 = 0; j2 < 16; ++j2) {
         const float2 kv = krow[j2];
         const int c = cb + 32 * sub + 2 * j2;
-        const uint64_t m0 = (row_ok && c < h) ? 0ull : ~0ull;
-        const uint64_t m1 = (row_ok && c + 1 < h) ? 0ull : ~0ull;
-        kk[2 * j2] = w_pack(kv.x, (uint32_t)c) | m0;
-        kk[2 * j2 + 1] = w_pack(kv.y, (uint32_t)(c + 1)) | m1;
+        const KT_ m0 = (row_ok && c < h) ? (KT_)0 : KO::kNone;
+        const KT_ m1 = (row_ok && c + 1 < h) ? (KT_)0 : KO::kNone;
+        kk[2 * j2] = KO::pack(kv.x, (uint32_t)c) | m0;
+        kk[2 * j2 + 1] = KO::pack(kv.y, (uint32_t)(c + 1)) | m1;
       }
-      const uint64_t* cur = &sm.lst[par][row * (KL + 1)];
-      uint64_t* nxt = &sm.lst[par ^ 1][row * (KL + 1)];
+      const KT_* cur = &sm.lst[par][row * (KL + 1)];
+      KT_* nxt = &sm.lst[par ^ 1][row * (KL + 1)];
       const int len = row_ok ? sm.rlen[row] : 0;
-      const float band = PREC == PREC_F32 ? 0.f : band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax;
+      // approximate keys: the error band plus the rounding of 32-bit keys
+      const float band = PREC == PREC_F32 ? 0.f
+                                          : band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax +
+                                                1.2207e-4f * (sm.qmax * sm.qmax + 2.f * sqrtf(sm.rvn[row]) * sm.qmax);
       int ptr = 0, w = 0;
       float P = 0.f, K0 = 0.f;
       bool cut = false;
-      uint64_t last = 0;
+      KT_ last = 0;
       bool act = row_ok;
       while (__any(act)) {
-        uint64_t best = ~0ull;
+        KT_ best = KO::kNone;
         if (act) {
 #pragma unroll
-          for (int j = 0; j < 32; ++j)
-            if (kk[j] > last && kk[j] < best) best = kk[j];
+          for (int j = 0; j < 32; ++j) {
+            const KT_ cand = kk[j] > last ? kk[j] : KO::kNone;
+            best = cand < best ? cand : best;
+          }
         }
-        const uint64_t o = w_shfl1(best);
+        const KT_ o = KO::shfl1(best);
         best = o < best ? o : best;
         if (act) {
-          const uint64_t lc = ptr < len ? cur[ptr] : ~0ull;
-          const uint64_t take = lc < best ? lc : best;
-          if (take == ~0ull) {
+          const KT_ lc = ptr < len ? cur[ptr] : KO::kNone;
+          const KT_ take = lc < best ? lc : best;
+          if (take == KO::kNone) {
             act = false;
-          } else if (cut && (PREC == PREC_F32 || w_unpack(take) > K0 + band)) {
+          } else if (cut && (PREC == PREC_F32 || KO::key(take) > K0 + band)) {
             act = false;
           } else if (w >= KL) {
             // the list is full: remember the smallest key left out; the
             // final lists are certified against it after the exact re-sort
             act = false;
-            if (sub == 0) sm.rdrop[row] = fminf(sm.rdrop[row], w_unpack(take));
+            if (sub == 0) sm.rdrop[row] = fminf(sm.rdrop[row], KO::key(take));
           } else {
             if (lc < best) ++ptr;
             else last = best;
             if (sub == 0) nxt[w] = take;
             ++w;
             if (!cut) {
-              P += sm.cap[(uint32_t)take];
+              P += sm.cap[KO::pos(take)];
               if (w >= kef || (kCapStop && P >= bound)) {
                 cut = true;
-                K0 = w_unpack(take);
+                K0 = KO::key(take);
               }
             }
           }
@@ -507,7 +541,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
 
   // ---------------- exact distances of the final lists ----------------
   const int len = row_ok ? sm.rlen[row] : 0;
-  const uint64_t* L = &sm.lst[par][row * (KL + 1)];
+  const auto* L = &sm.lst[par][row * (KL + 1)];
   if constexpr (PREC == PREC_F32) {
     for (int l = sub; l < len; l += 2) {
       const uint64_t e = L[l];
@@ -526,7 +560,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     for (int e = 0; e < KH; ++e) {
       ex[e] = 0.f;
       const int l = sub + 2 * e;
-      ps[e] = l < len ? (int)(uint32_t)L[l] : 0;
+      ps[e] = l < len ? (int)KeyOps<PREC>::pos(L[l]) : 0;
     }
     const float* vr = a.V + (size_t)sm.rid[row] * a.m_pad;
     // chunks of D dims of all h segment vectors per LDS pass, as wide as
@@ -560,9 +594,12 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
   __syncthreads();
 
   if (sub == 0 && row_ok) {
-    uint64_t* Lw = &sm.lst[par][row * (KL + 1)];
+    auto* Lw = &sm.lst[par][row * (KL + 1)];
     float* Z2 = &sm.u.zb[row * (KL + 1)];
     if constexpr (PREC != PREC_F32) {
+      // exact re-sort by (squared distance, position); the list then holds
+      // positions
+      for (int i = 0; i < len; ++i) Lw[i] = KeyOps<PREC>::pos(Lw[i]);
       for (int i = 1; i < len; ++i) {
         const uint64_t e = w_pack(Z2[i], (uint32_t)Lw[i]);
         int j = i - 1;
@@ -571,7 +608,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
           Z2[j + 1] = Z2[j];
           --j;
         }
-        Lw[j + 1] = e;
+        Lw[j + 1] = (uint32_t)e;
         Z2[j + 1] = w_unpack(e);
       }
     }
