@@ -100,10 +100,11 @@ __device__ __forceinline__ float exact_d2(const float* __restrict__ V, int m_pad
 
 }  // namespace
 
+// One work item: (query, 64-row block) in the table modes, (pair, row
+// block) in pair mode.  Returns early (uniformly) for empty items.
 template <int MODE, int KL, int PREC>
-__global__ __launch_bounds__(kThreads, 2) void k_phase1_fast(P1Args a) {
+__device__ __forceinline__ void fast_task(const P1Args& a, unsigned char* smem_raw, int64_t item) {
   using Sm = FastSmem<KL>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   Sm& sm = *reinterpret_cast<Sm*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -112,8 +113,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_fast(P1Args a) {
   int64_t out_row0 = 0, pidx = 0;
   int rb = 0;
   if constexpr (MODE == P1_PAIR) {
-    pidx = blockIdx.x;
-    rb = blockIdx.y;
+    pidx = item / a.rb_max;
+    rb = (int)(item % a.rb_max);
     int64_t b, u;
     if (a.cand) {
       const int64_t qi = pidx / a.cand_use, c = pidx % a.cand_use;
@@ -151,11 +152,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_fast(P1Args a) {
     }
   } else {
     const int64_t nrb = (a.v_used + kRows - 1) / kRows;
-    const int64_t ngroups = (a.nq + kGroup - 1) / kGroup;
-    const int64_t total = ngroups * nrb * kGroup;
-    const int64_t per = (int64_t)gridDim.x / 8;
-    const int64_t work = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (work >= total) return;
+    const int64_t work = item;
     const int64_t qin = work % kGroup, t = work / kGroup;
     const int64_t rblk = t % nrb, g = t / nrb;
     const int64_t qi = g * kGroup + qin;
@@ -420,23 +417,43 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_fast(P1Args a) {
   }
 }
 
+// Persistent grid fed by per-XCD counters (as the 128-row kernel).
+template <int MODE, int KL, int PREC>
+__global__ __launch_bounds__(kThreads, 2) void k_phase1_fast(P1Args a, int64_t total) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int64_t s_item;
+  const int xcd = blockIdx.x & 7;
+  const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
+  while (true) {
+    __syncthreads();  // the previous item is done with LDS and s_item
+    if (threadIdx.x == 0) s_item = lo + (int64_t)atomicAdd(&a.work_ctr[xcd], 1ull);
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= hi) break;
+    fast_task<MODE, KL, PREC>(a, smem_raw, item);
+  }
+}
+
 template <int MODE, int KL, int PREC>
 static hipError_t launch_fast_one(const P1Args& a, hipStream_t s) {
   const size_t shmem = sizeof(FastSmem<KL>);
-  hipError_t e = hipFuncSetAttribute((const void*)k_phase1_fast<MODE, KL, PREC>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  const void* fn = (const void*)k_phase1_fast<MODE, KL, PREC>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
-  dim3 grid;
+  int64_t total;
   if (MODE == P1_PAIR) {
-    grid = dim3((unsigned)a.npairs, (unsigned)a.rb_max, 1);
+    total = a.npairs * (int64_t)a.rb_max;
   } else {
     const int64_t nrb = (a.v_used + kRows - 1) / kRows;
-    const int64_t total = (a.nq + kGroup - 1) / kGroup * nrb * kGroup;
-    const int64_t blocks = (total + 7) / 8 * 8;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    grid = dim3((unsigned)blocks, 1, 1);
+    total = (a.nq + kGroup - 1) / kGroup * nrb * kGroup;
   }
-  hipLaunchKernelGGL((k_phase1_fast<MODE, KL, PREC>), grid, dim3(kThreads), shmem, s, a);
+  if (total <= 0) return hipSuccess;
+  if (!a.work_ctr) return hipErrorInvalidValue;
+  e = launch_zero_ints((int*)a.work_ctr, 16, s);
+  if (e != hipSuccess) return e;
+  const int grid = persistent_grid(fn, kThreads, shmem, total);
+  if (grid <= 0) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_phase1_fast<MODE, KL, PREC>), dim3(grid), dim3(kThreads), shmem, s, a, total);
   return hipGetLastError();
 }
 
