@@ -395,7 +395,7 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     if ((rc = prof_begin(c, "phase2", a2))) return rc;
     unsigned long long* p2c;
     if ((rc = wsget(c, "p2_counters", 8, p2c))) return rc;
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, ZW, nq, KT, nq, nullptr,
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, ZW, nq, KT, nq, nullptr,
                                        out + q0 * ld, ld, p2c, c->stream));
     if ((rc = prof_end(c))) return rc;
     q0 += nq;

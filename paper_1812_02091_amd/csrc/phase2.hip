@@ -21,7 +21,11 @@
 
 namespace lcemd {
 
-constexpr int kQB = 16;  // queries per work item (one contiguous table run per non-zero)
+// Queries per work item (one contiguous table run per non-zero): 16 when
+// the database is large (fewer passes over X), 8 otherwise (half the
+// registers, twice the resident waves for a latency-bound gather).
+constexpr int kQBLarge = 16, kQBSmall = 8;
+constexpr int64_t kLargeX = int64_t(64) << 20;  // bytes of X records
 constexpr int kItemDocs = 16;  // database rows per work item of the persistent kernel
 
 __device__ __forceinline__ float wave_sum(float t) {
@@ -47,6 +51,7 @@ __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
 // before any is consumed (the walk along a row is a chain of dependent
 // loads otherwise).  Entries past a row's sink are never used: the sink
 // leaves no mass.
+template <int kQB>
 __device__ __forceinline__ void doc_costs(int lane, int64_t u, int64_t q0, int nqb,
                                           const int64_t* __restrict__ xptr,
                                           const int2* __restrict__ xcv,
@@ -106,7 +111,8 @@ __device__ __forceinline__ void doc_costs(int lane, int64_t u, int64_t q0, int n
 // keeps a few queries' tables hot in its L2).  For fixed-shape batches the
 // live query count is read from device memory.  Every wave exits once its
 // counter passes the end of its range.
-__global__ __launch_bounds__(kThreads) void k_phase2_persistent(
+template <int kQB>
+__global__ __launch_bounds__(kThreads, kQB == kQBSmall ? 4 : 1) void k_phase2_persistent(
     const int64_t* __restrict__ xptr, const int2* __restrict__ xcv, int64_t n,
     const float4* __restrict__ ZP, int64_t zw_nq, int KP, int64_t nq_arg,
     const int* __restrict__ nq_dev, float* __restrict__ out, int64_t ld,
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
     for (int j = 0; j < kItemDocs; ++j) {
       const int64_t u = ubase + j;
       if (u >= n) break;
-      doc_costs(lane, u, q0, nqb, xptr, xcv, ZP, zw_nq, KP, out, ld);
+      doc_costs<kQB>(lane, u, q0, nqb, xptr, xcv, ZP, zw_nq, KP, out, ld);
     }
   }
 }
@@ -177,20 +183,29 @@ int persistent_grid(const void* fn, int threads, size_t shmem, int64_t items) {
   return (int)grid;
 }
 
-hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n,
+template <int kQB>
+static hipError_t launch_p2(const int64_t* xptr, const int2* xcv, int64_t n, const float2* ZW,
+                            int64_t zw_nq, int KT, int64_t nq, const int* nq_dev, float* out,
+                            int64_t ld, unsigned long long* counters, hipStream_t s) {
+  // items (one per wave) bound the grid when the batch size is known here
+  const int64_t items = nq_dev ? INT64_MAX / 2 : (nq + kQB - 1) / kQB * ((n + kItemDocs - 1) / kItemDocs) * 64;
+  const int grid = persistent_grid((const void*)k_phase2_persistent<kQB>, kThreads, 0, items);
+  if (grid <= 0) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_phase2_persistent<kQB>, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n,
+                     (const float4*)ZW, zw_nq, (int)zw_pairs(KT), nq, nq_dev, out, ld, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n, int64_t nnz,
                                     const float2* ZW, int64_t zw_nq, int KT, int64_t nq,
                                     const int* nq_dev, float* out, int64_t ld,
                                     unsigned long long* counters, hipStream_t s) {
   if (n <= 0 || (!nq_dev && nq <= 0)) return hipSuccess;
   hipError_t e = launch_zero_ints((int*)counters, 16, s);
   if (e != hipSuccess) return e;
-  // items (one per wave) bound the grid when the batch size is known here
-  const int64_t items = nq_dev ? INT64_MAX / 2 : (nq + kQB - 1) / kQB * ((n + kItemDocs - 1) / kItemDocs) * 64;
-  const int grid = persistent_grid((const void*)k_phase2_persistent, kThreads, 0, items);
-  if (grid <= 0) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_phase2_persistent, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n,
-                     (const float4*)ZW, zw_nq, (int)zw_pairs(KT), nq, nq_dev, out, ld, counters);
-  return hipGetLastError();
+  if (nnz * 8 > kLargeX)
+    return launch_p2<kQBLarge>(xptr, xcv, n, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
+  return launch_p2<kQBSmall>(xptr, xcv, n, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
 }
 
 __global__ __launch_bounds__(kThreads) void k_max_inplace(float* a, const float* b, int64_t count) {
