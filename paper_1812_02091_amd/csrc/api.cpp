@@ -355,18 +355,18 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     a.ZW = ZW;
     a.zw_nq = nq;
     a.overflow = ovf;
+    // rows whose quantised selection is not certified are listed for an
+    // exact redo (every precision on the 128-row kernel)
     int* fixc = nullptr;
-    if (prec != LCEMD_FP32) {
-      if ((rc = wsget(c, "fix_count", 1, fixc)) || (rc = wsget(c, "fix_list", kFixCap, a.fix_list))) return rc;
-      HIPCHK(c, hipMemsetAsync(fixc, 0, sizeof(int), c->stream));
-      a.fix_count = fixc;
-      a.fix_cap = kFixCap;
-    }
+    if ((rc = wsget(c, "fix_count", 1, fixc)) || (rc = wsget(c, "fix_list", kFixCap, a.fix_list))) return rc;
+    HIPCHK(c, hipMemsetAsync(fixc, 0, sizeof(int), c->stream));
+    a.fix_count = fixc;
+    a.fix_cap = kFixCap;
     int64_t H = Q.hptr[q0 + nq] - Q.hptr[q0];
     if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)c->v_used * (double)H * (double)c->m))) return rc;
     if ((rc = p1_launch(c, a, P1_TABLE, prec, KT, Q.hmax, Q.hmax))) return rc;
     if ((rc = prof_end(c))) return rc;
-    if ((o->method == LCEMD_ICT && KT < Q.hmax) || prec != LCEMD_FP32) {
+    {
       int h_ovf = 0, h_fix = 0;
       HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       if (fixc) HIPCHK(c, hipMemcpyAsync(&h_fix, fixc, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -876,7 +876,7 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
   a.fix_count = fixc;
   a.fix_cap = kFixCap;
   if ((rc = p1_launch(c, a, P1_TABLE_FULL, o->precision, o->k, Q.hmax, Q.hmax))) return rc;
-  if (o->precision != LCEMD_FP32) {
+  {
     int h_ovf = 0, h_fix = 0;
     HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&h_fix, fixc, sizeof(int), hipMemcpyDeviceToHost, c->stream));

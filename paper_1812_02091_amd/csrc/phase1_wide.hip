@@ -73,12 +73,14 @@ __device__ __forceinline__ uint64_t w_shfl1(uint64_t v) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
 }
 
-// Selection keys.  float32 keys: (order-preserving key bits, position) in
-// 64 bits, exact order.  bf16/fp8 keys are approximate anyway (a band and an
-// exact re-sort follow), so they drop the key's 9 low bits for the position
-// (positions < 512): one 32-bit word, rounded down in value by at most
-// 2^-14 of the key's magnitude, which the band covers.
-template <int PREC>
+// Selection keys.  Exact keys: (order-preserving key bits, position) in 64
+// bits (float32 pair mode).  Quantised keys (the table modes): the key's 9
+// low bits give way to the position (positions < 512), one 32-bit word,
+// rounded down in value by at most 2^-14 of the key's magnitude; lists keep
+// every entry within that band past their cut and are re-sorted afterwards
+// by the exact keys (float32: the contraction's key, kept beside the list;
+// bf16/fp8: the recomputed distances).
+template <bool QK>
 struct KeyOps {
   using T = uint32_t;
   static constexpr T kNone = 0xffffffffu;
@@ -91,7 +93,7 @@ struct KeyOps {
   __device__ static T shfl1(T v) { return (T)__shfl_xor((int)v, 1); }
 };
 template <>
-struct KeyOps<PREC_F32> {
+struct KeyOps<false> {
   using T = uint64_t;
   static constexpr T kNone = ~0ull;
   __device__ static T pack(float f, uint32_t pos) { return w_pack(f, pos); }
@@ -197,15 +199,17 @@ __device__ __forceinline__ void slice_mfma(int ntile, floatx16 (&acc)[4], const 
   }
 }
 
-template <int KL, int PREC>
+template <int KL, int PREC, bool QK, bool EX>
 struct WideSmem {
+  static constexpr int KLS = KL + 1 + (EX ? 1 : 0);  // list row stride (odd or +1: spreads rows over banks)
   union {
     unsigned char st[kWC * kStride];  // staged column slice
     float ck[kWR * kCK];              // keys of 64 columns of a pass
     float qs[PREC == PREC_F32 ? 1 : kQSCap];  // segment vectors, a chunk of dims (exact recompute)
-    float zb[kWR * (KL + 1)];         // exact squared distances of the lists
+    float zb[kWR * KLS];              // exact squared distances of the lists
   } u;
-  typename KeyOps<PREC>::T lst[2][kWR * (KL + 1)];  // row stride KL + 1 spreads rows over LDS banks
+  typename KeyOps<QK>::T lst[2][kWR * KLS];
+  float lkx[EX ? 2 : 1][EX ? kWR * KLS : 1];  // float32 quantised keys: the exact keys beside the list
   int cid[kSeg];
   float cap[kSeg];
   float qn[kSeg];
@@ -268,7 +272,13 @@ __device__ __forceinline__ void wide_dots(float (&ex)[KH], const int (&ps)[KH], 
 // block) in pair mode.  Returns early (uniformly) for empty items.
 template <int MODE, int KL, int PREC>
 __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_raw, int64_t item) {
-  using Sm = WideSmem<KL, PREC>;
+  // quantised keys everywhere but in the float32 pair mode; EX: float32
+  // with quantised keys keeps the exact keys and one more list slot
+  constexpr bool QK = PREC != PREC_F32 || MODE != P1_PAIR;
+  constexpr bool EX = PREC == PREC_F32 && QK;
+  constexpr int KLC = KL + (EX ? 1 : 0);  // list capacity
+  using Sm = WideSmem<KL, PREC, QK, EX>;
+  constexpr int KLS = Sm::KLS;
   Sm& sm = *reinterpret_cast<Sm*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -354,7 +364,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
   }
   if (tid == 0) sm.qmax = 0.f;
   __syncthreads();
-  if (PREC != PREC_F32 && tid < 64) {
+  if (QK && tid < 64) {
     float mx = 0.f;
     for (int c = tid; c < h; c += 64) mx = fmaxf(mx, sm.qn[c]);
     for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
@@ -466,7 +476,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       __syncthreads();
       // this thread's 32 contiguous columns, read without branches (the
       // buffer is fully allocated; columns past h are masked afterwards)
-      using KO = KeyOps<PREC>;
+      using KO = KeyOps<QK>;
       using KT_ = typename KO::T;
       KT_ kk[32];
       const float2* krow = (const float2*)&sm.u.ck[row * kCK + 32 * sub];
@@ -479,13 +489,15 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
         kk[2 * j2] = KO::pack(kv.x, (uint32_t)c) | m0;
         kk[2 * j2 + 1] = KO::pack(kv.y, (uint32_t)(c + 1)) | m1;
       }
-      const KT_* cur = &sm.lst[par][row * (KL + 1)];
-      KT_* nxt = &sm.lst[par ^ 1][row * (KL + 1)];
+      const KT_* cur = &sm.lst[par][row * KLS];
+      KT_* nxt = &sm.lst[par ^ 1][row * KLS];
+      const float* curx = &sm.lkx[EX ? par : 0][EX ? row * KLS : 0];
+      float* nxtx = &sm.lkx[EX ? (par ^ 1) : 0][EX ? row * KLS : 0];
       const int len = row_ok ? sm.rlen[row] : 0;
       // approximate keys: the error band plus the rounding of 32-bit keys
-      const float band = PREC == PREC_F32 ? 0.f
-                                          : band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax +
-                                                1.2207e-4f * (sm.qmax * sm.qmax + 2.f * sqrtf(sm.rvn[row]) * sm.qmax);
+      const float band = !QK ? 0.f
+                             : band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax +
+                                   1.2207e-4f * (sm.qmax * sm.qmax + 2.f * sqrtf(sm.rvn[row]) * sm.qmax);
       int ptr = 0, w = 0;
       float P = 0.f, K0 = 0.f;
       bool cut = false;
@@ -507,14 +519,17 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
           const KT_ take = lc < best ? lc : best;
           if (take == KO::kNone) {
             act = false;
-          } else if (cut && (PREC == PREC_F32 || KO::key(take) > K0 + band)) {
+          } else if (cut && (!QK || KO::key(take) > K0 + band)) {
             act = false;
-          } else if (w >= KL) {
+          } else if (w >= KLC) {
             // the list is full: remember the smallest key left out; the
             // final lists are certified against it after the exact re-sort
             act = false;
             if (sub == 0) sm.rdrop[row] = fminf(sm.rdrop[row], KO::key(take));
           } else {
+            if constexpr (EX) {
+              if (sub == 0) nxtx[w] = lc < best ? curx[ptr] : sm.u.ck[row * kCK + (int)(KO::pos(take)) - cb];
+            }
             if (lc < best) ++ptr;
             else last = best;
             if (sub == 0) nxt[w] = take;
@@ -541,16 +556,16 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
 
   // ---------------- exact distances of the final lists ----------------
   const int len = row_ok ? sm.rlen[row] : 0;
-  const auto* L = &sm.lst[par][row * (KL + 1)];
+  const auto* L = &sm.lst[par][row * KLS];
   if constexpr (PREC == PREC_F32) {
     for (int l = sub; l < len; l += 2) {
-      const uint64_t e = L[l];
-      const int pos = (int)(uint32_t)e;
-      float d2 = sm.rvn[row] + w_unpack(e);
+      const auto e = L[l];
+      const int pos = (int)KeyOps<QK>::pos(e);
+      float d2 = sm.rvn[row] + (EX ? sm.lkx[EX ? par : 0][EX ? row * KLS + l : 0] : KeyOps<QK>::key(e));
       bool need = !(d2 >= kGuardW * (sm.rvn[row] + sm.qn[pos]));
       if (MODE != P1_TABLE_FULL && a.method == LCEMD_OMR && l == 0) need = true;
       if (need) d2 = w_exact_d2(a.V, a.m_pad, sm.rid[row], sm.cid[pos]);
-      sm.u.zb[row * (KL + 1) + l] = d2;
+      sm.u.zb[row * KLS + l] = d2;
     }
   } else {
     constexpr int KH = (KL + 1) / 2;
@@ -560,7 +575,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     for (int e = 0; e < KH; ++e) {
       ex[e] = 0.f;
       const int l = sub + 2 * e;
-      ps[e] = l < len ? (int)KeyOps<PREC>::pos(L[l]) : 0;
+      ps[e] = l < len ? (int)KeyOps<QK>::pos(L[l]) : 0;
     }
     const float* vr = a.V + (size_t)sm.rid[row] * a.m_pad;
     // chunks of D dims of all h segment vectors per LDS pass, as wide as
@@ -588,18 +603,37 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
 #pragma unroll
     for (int e = 0; e < KH; ++e) {
       const int l = sub + 2 * e;
-      if (l < len) sm.u.zb[row * (KL + 1) + l] = ex[e];
+      if (l < len) sm.u.zb[row * KLS + l] = ex[e];
     }
   }
   __syncthreads();
 
   if (sub == 0 && row_ok) {
-    auto* Lw = &sm.lst[par][row * (KL + 1)];
-    float* Z2 = &sm.u.zb[row * (KL + 1)];
-    if constexpr (PREC != PREC_F32) {
+    auto* Lw = &sm.lst[par][row * KLS];
+    float* Z2 = &sm.u.zb[row * KLS];
+    float* Lx = &sm.lkx[EX ? par : 0][EX ? row * KLS : 0];
+    if constexpr (EX) {
+      // exact re-sort by (contraction key, position), distances moving
+      // along; the list then holds positions
+      for (int i = 0; i < len; ++i) Lw[i] = KeyOps<QK>::pos(Lw[i]);
+      for (int i = 1; i < len; ++i) {
+        const uint64_t e = w_pack(Lx[i], (uint32_t)Lw[i]);
+        const float z = Z2[i];
+        int j = i - 1;
+        while (j >= 0 && w_pack(Lx[j], (uint32_t)Lw[j]) > e) {
+          Lw[j + 1] = Lw[j];
+          Lx[j + 1] = Lx[j];
+          Z2[j + 1] = Z2[j];
+          --j;
+        }
+        Lw[j + 1] = (uint32_t)e;
+        Lx[j + 1] = w_unpack(e);
+        Z2[j + 1] = z;
+      }
+    } else if constexpr (PREC != PREC_F32) {
       // exact re-sort by (squared distance, position); the list then holds
       // positions
-      for (int i = 0; i < len; ++i) Lw[i] = KeyOps<PREC>::pos(Lw[i]);
+      for (int i = 0; i < len; ++i) Lw[i] = KeyOps<QK>::pos(Lw[i]);
       for (int i = 1; i < len; ++i) {
         const uint64_t e = w_pack(Z2[i], (uint32_t)Lw[i]);
         int j = i - 1;
@@ -633,10 +667,17 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     if (!covered && D < h && a.overflow) a.overflow[0] = 1;
     // a candidate left out of a full list has a key >= rdrop - half a band
     // (bf16; exact keys for float32): the used entries must all be nearer
-    if (PREC != PREC_F32 && D > 0 && sm.rdrop[row] < INFINITY && a.overflow) {
-      const float half_band = PREC == PREC_F32 ? 0.f : 0.5f * band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax;
-      const float last_key = Z2[D - 1] - sm.rvn[row];
-      if (!(last_key < sm.rdrop[row] - half_band - 1e-6f * (sm.rvn[row] + sm.qmax * sm.qmax))) {
+    if (QK && D > 0 && sm.rdrop[row] < INFINITY && a.overflow) {
+      bool certified;
+      if constexpr (EX) {
+        // exact keys left out are at least their quantised value
+        certified = Lx[D - 1] < sm.rdrop[row];
+      } else {
+        const float half_band = 0.5f * band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax;
+        const float last_key = Z2[D - 1] - sm.rvn[row];
+        certified = last_key < sm.rdrop[row] - half_band - 1e-6f * (sm.rvn[row] + sm.qmax * sm.qmax);
+      }
+      if (!certified) {
         // redo this row exactly (k_fix_rows) unless the list of such rows is full
         int slot = a.fix_cap;
         if (MODE != P1_PAIR && a.fix_list) slot = atomicAdd(a.fix_count, 1);
@@ -707,7 +748,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a, int64_t t
 
 template <int MODE, int KL, int PREC>
 static hipError_t launch_wide_one(const P1Args& a, hipStream_t s) {
-  const size_t shmem = sizeof(WideSmem<KL, PREC>);
+  constexpr bool QK = PREC != PREC_F32 || MODE != P1_PAIR;
+  const size_t shmem = sizeof(WideSmem<KL, PREC, QK, PREC == PREC_F32 && QK>);
   const void* fn = (const void*)k_phase1_wide<MODE, KL, PREC>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;

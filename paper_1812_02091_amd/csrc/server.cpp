@@ -185,13 +185,11 @@ int issue(lcemd_server* s, Lane& L) {
     a.zw_nq = s->B;
     a.overflow = L.ints + 8;
     a.work_ctr = L.ctr;
-    if (s->prec != LCEMD_FP32) {
-      a.fix_count = L.ints + 9;
-      a.fix_list = L.fixl;
-      a.fix_cap = kFixCapLane;
-    }
+    a.fix_count = L.ints + 9;
+    a.fix_list = L.fixl;
+    a.fix_cap = kFixCapLane;
     if ((rc = p1_launch(c, a, P1_TABLE, s->prec, s->KT, LCEMD_MAX_HIST, LCEMD_MAX_HIST))) break;
-    if (s->prec != LCEMD_FP32) HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
+    HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
     HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, L.ZW, s->B, s->KT, s->B, L.nq,
                                        L.d2q, c->n, L.ctr + 8, L.stream));
     HIPCHK(c, launch_select(L.d2q, c->n, c->n, s->B, s->cld, nullptr, -1, L.cand, L.seltmp, L.stream));
