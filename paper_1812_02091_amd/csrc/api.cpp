@@ -227,7 +227,7 @@ int check_opts(lcemd_ctx* c, const lcemd_opts* o) {
 }
 
 constexpr int kMargin = 8;  // over-selection for approximate (bf16/fp8) keys
-constexpr int kFixCap = 1 << 20;  // rows per launch that may be redone exactly
+constexpr int kFixCap = 1 << 23;  // rows per launch that may be redone exactly (64 MB list)
 
 int pow2ceil(int x) {
   int p = 2;
@@ -346,14 +346,14 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     Bt = std::min<int64_t>(Bt, 65535);
     const int64_t nq = std::min<int64_t>(Bt, Q.B - q0);
     float2* ZW;
-    if ((rc = wsget(c, "zw", (size_t)nq * c->v_used * 2 * zw_pairs(KT), ZW))) return rc;
+    if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * c->v_used * 2 * zw_pairs(KT), ZW))) return rc;
     HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
     P1Args a = base_args(c, Q, o);
     a.KT = KT;
     a.q0 = q0;
     a.nq = nq;
     a.ZW = ZW;
-    a.zw_nq = nq;
+    a.zw_nq = zw_pitch(nq);
     a.overflow = ovf;
     // rows whose quantised selection is not certified are listed for an
     // exact redo (every precision on the 128-row kernel)
@@ -382,12 +382,9 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
       if (h_ovf) {
         // a row needed more list entries than the kernel keeps: redo the tile
         // with float32 keys, and for ICT with full-depth tables
-        if (prec != LCEMD_FP32) {
-          prec = LCEMD_FP32;
-          ++c->fallbacks;
-        } else {
-          KT = Q.hmax;
-        }
+        ++c->fallbacks;
+        if (prec != LCEMD_FP32) prec = LCEMD_FP32;
+        else KT = Q.hmax;
         continue;
       }
     }
@@ -395,7 +392,7 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     if ((rc = prof_begin(c, "phase2", a2))) return rc;
     unsigned long long* p2c;
     if ((rc = wsget(c, "p2_counters", 8, p2c))) return rc;
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, ZW, nq, KT, nq, nullptr,
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, ZW, a.zw_nq, KT, nq, nullptr,
                                        out + q0 * ld, ld, p2c, c->stream));
     if ((rc = prof_end(c))) return rc;
     q0 += nq;

@@ -90,8 +90,13 @@ struct P1Args {
 // next to pair p of the same word for every query of the table, so that
 // phase 2 reads a word's first pair for a group of queries as one
 // contiguous run: float2 index ((r * KP + p) * zw_nq + qi) * 2 + (l & 1),
-// KP = ceil(KT / 2).  Tables hold zw_nq * v_used * KP float4.
+// KP = ceil(KT / 2), zw_nq = zw_pitch(queries of the table).  Tables hold
+// zw_nq * v_used * KP float4.
 __host__ __device__ inline int64_t zw_pairs(int KT) { return (KT + 1) >> 1; }
+// Queries per table run, padded so that consecutive words' runs are not a
+// multiple of a large power of two apart (which would send a word-strided
+// gather to few memory channels).
+__host__ __device__ inline int64_t zw_pitch(int64_t nq) { return (nq + 15) / 16 * 16 + 16; }
 __device__ __forceinline__ float4* zw_pair(float2* ZW, int64_t zw_nq, int KT, int64_t qi, int64_t r,
                                            int p) {
   return (float4*)ZW + (r * zw_pairs(KT) + p) * zw_nq + qi;

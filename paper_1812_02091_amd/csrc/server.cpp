@@ -182,7 +182,7 @@ int issue(lcemd_server* s, Lane& L) {
     a.nq = s->B;
     a.KT = s->KT;
     a.ZW = L.ZW;
-    a.zw_nq = s->B;
+    a.zw_nq = zw_pitch(s->B);
     a.overflow = L.ints + 8;
     a.work_ctr = L.ctr;
     a.fix_count = L.ints + 9;
@@ -190,7 +190,7 @@ int issue(lcemd_server* s, Lane& L) {
     a.fix_cap = kFixCapLane;
     if ((rc = p1_launch(c, a, P1_TABLE, s->prec, s->KT, LCEMD_MAX_HIST, LCEMD_MAX_HIST))) break;
     HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, L.ZW, s->B, s->KT, s->B, L.nq,
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, L.ZW, zw_pitch(s->B), s->KT, s->B, L.nq,
                                        L.d2q, c->n, L.ctr + 8, L.stream));
     HIPCHK(c, launch_select(L.d2q, c->n, c->n, s->B, s->cld, nullptr, -1, L.cand, L.seltmp, L.stream));
     P1Args p = a;
@@ -221,7 +221,7 @@ int setup_lane(lcemd_server* s, Lane& L) {
   if ((rc = dalloc(c, L.qptr, B + 1, "lane")) || (rc = dalloc(c, L.qcol, W, "lane")) ||
       (rc = dalloc(c, L.qval, W, "lane")) || (rc = dalloc(c, L.nq, 1, "lane")) ||
       (rc = dalloc(c, L.ints, 16, "lane")) || (rc = dalloc(c, L.ctr, 16, "lane")) || (rc = dalloc(c, L.fixl, kFixCapLane, "lane")) ||
-      (rc = dalloc(c, L.ZW, B * c->v_used * 2 * zw_pairs(s->KT), "lane tables")) ||
+      (rc = dalloc(c, L.ZW, zw_pitch(B) * c->v_used * 2 * zw_pairs(s->KT), "lane tables")) ||
       (rc = dalloc(c, L.d2q, B * n, "lane")) || (rc = dalloc(c, L.cand, B * s->cld, "lane")) ||
       (rc = dalloc(c, L.seltmp, select_tmp_elems(B, n, s->cld), "lane")) ||
       (rc = dalloc(c, L.q2dv, B * s->use, "lane")) ||
