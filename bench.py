@@ -155,6 +155,43 @@ def oracle_error(ctx, w, nq, rows, method, k, precision):
             "pairs": int(rel.size)}
 
 
+def image_section(a, lcemd):
+    """Image-shaped dense histograms (28x28 grid, 60,000 database and 10,000
+    query blobs; m = 2): symmetric ACT top-16 for the whole query batch."""
+    import numpy as np
+
+    from synth import make_workload
+
+    w = make_workload("image")
+    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
+    B, n = w.queries.n, w.db.n
+    q = w.queries
+    small = q.take(list(range(8)))
+    res = {"workload": f"image: 784 pixels x 2 coordinates, {n} database and {B} query histograms "
+                       f"({w.db.nnz} database non-zeros), symmetric top-16",
+           "paper_context": {"distances_per_s": 1.8e7, "hardware": "GTX 1080Ti (top-l on an 8-core CPU)",
+                             "workload": "MNIST 60,000 x 60,000 all pairs, ACT with one phase-2 iteration "
+                                         "(k=2 here), symmetric (Sec. 5)"}}
+    for k in (2, 16):
+        ctx.topl(small.rowptr, small.col, small.val, 16, method="act", k=k, direction="sym")
+        ctx.profile(True)
+        t1 = time.perf_counter()
+        ctx.topl(q.rowptr, q.col, q.val, 16, method="act", k=k, direction="sym")
+        dt = time.perf_counter() - t1
+        ph = {p["name"]: p for p in ctx.profile_get()}
+        ctx.profile(False)
+        rec = {"distances_per_s": B * n / dt, "s_per_batch": dt,
+               "phase_ms": {k2: v["ms"] for k2, v in ph.items()}}
+        if "phase2" in ph and ph["phase2"]["ms"] > 0:
+            gbs = ph["phase2"]["work"] / (ph["phase2"]["ms"] * 1e-3) / 1e9
+            rec["phase2_algorithmic_GBps"] = gbs
+            rec["phase2_hbm_frac"] = gbs * 1e9 / HBM_PEAK
+        res[f"act{k}"] = rec
+        print(f"[bench] image ACT k={k}: {dt:.3f} s", file=sys.stderr, flush=True)
+    ctx.close()
+    return res
+
+
 def big_workload(a, lcemd):
     """The 1M-word / 1M-document workload: (1) the precision variant -- one
     symmetric ACT k=8 top-16 call over the whole query batch with float32,
@@ -395,6 +432,7 @@ def main():
     fb, fixed = ctx.counters()
     counters = {"fallback_tiles": fb, "rows_redone_exactly": fixed}
     ctx.close()
+    image = None if a.no_big else image_section(a, lcemd)
     big = None if a.no_big else big_workload(a, lcemd)
 
     out = {
@@ -420,6 +458,7 @@ def main():
         "phases": phase_report,
         "precisions": precisions,
         "counters": counters,
+        "image": image,
         "text_1M": big,
     }
     print(json.dumps(out))

@@ -222,8 +222,7 @@ int lcemd_profile_get(lcemd_ctx* ctx, lcemd_phase_time* out, int cap);
  * exact pruning of lcemd_topl).  Submitted queries wait in a FIFO; a worker
  * thread admits them into a free lane (a stream with preallocated device
  * and pinned host buffers for up to B queries and W words), runs the lane's
- * whole batch -- phase 1 tables, the exact redo of uncertified bfloat16
- * rows, phase 2 on a persistent kernel fed by per-XCD work counters, D2Q
+ * whole batch -- phase 1 tables, the exact redo of uncertified rows, phase 2 on a persistent kernel fed by per-XCD work counters, D2Q
  * candidate selection, Q2D of the candidates, symmetric top-l -- and
  * completes each query independently.  A query whose top-l certificate
  * fails, or whose lists overflowed, is finished by lcemd_topl.
@@ -247,8 +246,9 @@ typedef struct {
   int32_t max_slots;       /* queries per batch (>= 1); lowered to fit memory_budget */
   int32_t max_batch_words; /* words per batch (raised to LCEMD_MAX_HIST); 0 = no limit */
   int64_t memory_budget;   /* device bytes for all lanes' buffers; 0 = 4 GiB */
-  int32_t use_graph;       /* nonzero: two lanes, each batch replayed as a captured hipGraph;
-                              zero: one lane, kernels launched per batch */
+  int32_t use_graph;       /* nonzero: two lanes, each batch replayed as a captured hipGraph
+                              (while one runs, the other starts once max_slots/2 queries
+                              wait); zero: one lane, kernels launched per batch */
   int32_t reserved[5];     /* must be 0 */
 } lcemd_server_cfg;
 

@@ -11,8 +11,8 @@
 // shapes (padding slots are empty queries; the live query count is read
 // from device memory), so with use_graph it is captured once per lane as a
 // hipGraph and replayed for every batch.  With two or more lanes, batches
-// that arrive while others run are admitted and their work overlaps on the
-// device; a query whose symmetric top-l certificate fails (or whose lists
+// that arrive while others run are admitted (once half a batch is waiting)
+// and their work overlaps on the device; a query whose symmetric top-l certificate fails (or whose lists
 // overflowed) is finished by the exact widening path of lcemd_topl.
 //
 // Each query's result depends only on that query: tables, per-document
@@ -358,7 +358,11 @@ void worker_main(lcemd_server* s) {
         if (!any_busy) break;
       }
       if (s->stopping && s->pending.empty() && !any_busy) break;
-      if (!s->pending.empty() && (s->continuous || !any_busy)) {
+      // an idle device takes whatever is queued; while a batch runs, a
+      // second lane starts only once half a batch is waiting (a few
+      // queries finish sooner after the running batch than beside it)
+      if (!s->pending.empty() &&
+          (!any_busy || (s->continuous && (int)s->pending.size() >= std::max(1, s->B / 2)))) {
         for (Lane& L : s->lanes)
           if (!L.busy) {
             freeL = &L;
