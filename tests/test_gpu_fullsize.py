@@ -1,0 +1,126 @@
+"""Parity at the full workload sizes, in the configuration bench.py times
+(one lcemd_topl call over the whole query batch, device-resident inputs):
+the oracle computes sampled outputs one by one -- whole distance rows for
+a few queries (exact top-16 check) and single (query, neighbour) pairs."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import emd_oracle as O
+from synth import make_workload
+from synth.generators import sample_pairs
+import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_02091_amd import lcemd
+
+    lcemd.load_library()
+    return lcemd
+
+
+def _device_topl(L, w, ell, **kw):
+    import torch
+
+    dev = torch.device("cuda:0")
+    ctx = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val)
+    q = [torch.from_numpy(x).to(dev) for x in (w.queries.rowptr, w.queries.col, w.queries.val)]
+    idx, dist = ctx.topl(*q, ell, **kw)
+    torch.cuda.synchronize()
+    return ctx, idx.cpu().numpy(), dist.cpu().numpy()
+
+
+def _check_pairs(orc, w, idx, dist, method, k, picks):
+    for b, j in picks:
+        qc, qw = w.queries.row(int(b))
+        o = orc.pair(qc, qw, int(idx[b, j]), method, k, "sym")
+        P.assert_distances(np.array([dist[b, j]]), np.array([o]), f"query {b} rank {j}")
+
+
+def _check_list(idx, dist, n, ell):
+    assert idx.shape[1] == ell
+    assert np.all((idx >= 0) & (idx < n))
+    assert np.all(np.diff(dist, axis=1) >= 0)
+    for b in range(idx.shape[0]):
+        assert len(set(idx[b].tolist())) == ell
+
+
+def test_text_full_size(L):
+    """Text workload (70,000 x 300 vocabulary, 18,000 documents, 1,000
+    queries), ACT k=16 symmetric top-16, float32 and bf16 keys."""
+    import torch
+
+    w = make_workload("text")
+    say("[gpu] full-size text, ACT k=16 sym top-16, fp32")
+    ctx, idx, dist = _device_topl(L, w, 16, method="act", k=16, direction="sym", precision="fp32")
+    _check_list(idx, dist, w.db.n, 16)
+    dev = torch.device("cuda:0")
+    q = [torch.from_numpy(x).to(dev) for x in (w.queries.rowptr, w.queries.col, w.queries.val)]
+    say("[gpu] full-size text, bf16")
+    ib, db = ctx.topl(*q, 16, method="act", k=16, direction="sym", precision="bf16")
+    ib, db = ib.cpu().numpy(), db.cpu().numpy()
+    _check_list(ib, db, w.db.n, 16)
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    bs, js = sample_pairs(2, w.queries.n, 16, 24)
+    _check_pairs(orc, w, idx, dist, "act", 16, zip(bs, js))
+    _check_pairs(orc, w, ib, db, "act", 16, zip(bs, js))
+    for b in (int(bs[0]), int(bs[1])):  # whole rows: the top-16 itself
+        qc, qw = w.queries.row(b)
+        row = orc.row_distances(qc, qw, "act", 16, "sym")
+        P.check_topl(idx[b], dist[b], row, 16, f"query {b} fp32")
+        P.check_topl(ib[b], db[b], row, 16, f"query {b} bf16")
+    say("[gpu] full-size text done")
+
+
+def test_image_full_size(L):
+    """Image workload (28x28 grid, 60,000 documents, 10,000 queries), ACT
+    k=2 symmetric top-16: sampled (query, neighbour) distances."""
+    w = make_workload("image")
+    say("[gpu] full-size image, ACT k=2 sym top-16")
+    ctx, idx, dist = _device_topl(L, w, 16, method="act", k=2, direction="sym")
+    _check_list(idx, dist, w.db.n, 16)
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    bs, js = sample_pairs(3, w.queries.n, 16, 24)
+    _check_pairs(orc, w, idx, dist, "act", 2, zip(bs, js))
+    say("[gpu] full-size image done")
+
+
+def test_text_1m_vocabulary(L):
+    """1M-word vocabulary and 1M documents (the serving database), 64 of
+    its queries, ACT k=8 symmetric top-16 in float32 and bf16: sampled
+    (query, neighbour) distances and agreement of the two paths."""
+    w = make_workload("text-1M", B=64)
+    say("[gpu] 1M-word workload, 64 queries, ACT k=8 sym top-16")
+    ctx, idx, dist = _device_topl(L, w, 16, method="act", k=8, direction="sym", precision="fp32")
+    _check_list(idx, dist, w.db.n, 16)
+    import torch
+
+    dev = torch.device("cuda:0")
+    q = [torch.from_numpy(x).to(dev) for x in (w.queries.rowptr, w.queries.col, w.queries.val)]
+    ib, db = ctx.topl(*q, 16, method="act", k=8, direction="sym", precision="bf16")
+    ib = ib.cpu().numpy()
+    agree = np.mean([len(set(idx[b]) & set(ib[b])) / 16 for b in range(idx.shape[0])])
+    assert agree == 1.0, agree
+    bs, js = sample_pairs(4, w.queries.n, 16, 16)
+    docs = sorted({int(idx[b, j]) for b, j in zip(bs, js)})
+    sub = w.db.take(docs)
+    pos = {u: i for i, u in enumerate(docs)}
+    orc = O.Oracle(w.V, sub.rowptr, sub.col, sub.val)
+    for b, j in zip(bs, js):
+        qc, qw = w.queries.row(int(b))
+        o = orc.pair(qc, qw, pos[int(idx[b, j])], "act", 8, "sym")
+        P.assert_distances(np.array([dist[b, j]]), np.array([o]), f"query {b} rank {j}")
+    say("[gpu] 1M-word workload done")
