@@ -192,6 +192,38 @@ def image_section(a, lcemd):
     return res
 
 
+def selfjoin_section(a, lcemd):
+    """All-pairs protocol of Sec. 5 at the MNIST training-set shape: every one
+    of 60,000 image histograms against all 60,000 (itself excluded), ACT
+    k=2 symmetric, top-16 neighbours per histogram, one lcemd_selfjoin_topl."""
+    from synth import make_workload
+
+    w = make_workload("image", B=8)
+    n = w.db.n
+    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
+    res = {"workload": f"image self-join: {n} histograms on the 28x28 grid ({w.db.nnz} non-zeros), "
+                       f"all {n}x{n} pairs, ACT k=2 symmetric, top-16 per histogram",
+           "paper_context": {"seconds": 3.3 * 60, "distances_per_s": 3.6e9 / (3.3 * 60),
+                             "hardware": "GTX 1080Ti",
+                             "workload": "MNIST 60,000 training images, all pairs, ACT-1 (Sec. 5)"}}
+    small = lcemd.open_context(w.V, w.db.rowptr[:65], w.db.col[:w.db.rowptr[64]], w.db.val[:w.db.rowptr[64]],
+                               device=0)
+    small.selfjoin_topl(16, method="act", k=2, direction="sym")  # loads kernels
+    small.close()
+    ctx.selfjoin_topl(16, method="act", k=2, direction="sym")  # workspace
+    ctx.profile(True)
+    t1 = time.perf_counter()
+    ctx.selfjoin_topl(16, method="act", k=2, direction="sym")
+    dt = time.perf_counter() - t1
+    ph = {p["name"]: p["ms"] for p in ctx.profile_get()}
+    ctx.profile(False)
+    ctx.close()
+    res.update({"seconds": dt, "distances_per_s": n * n / dt, "phase_ms": ph,
+                "speedup_vs_paper": (3.3 * 60) / dt})
+    print(f"[bench] image self-join {n}x{n}: {dt:.3f} s", file=sys.stderr, flush=True)
+    return res
+
+
 def big_workload(a, lcemd):
     """The 1M-word / 1M-document workload: (1) the precision variant -- one
     symmetric ACT k=8 top-16 call over the whole query batch with float32,
@@ -433,6 +465,7 @@ def main():
     counters = {"fallback_tiles": fb, "rows_redone_exactly": fixed}
     ctx.close()
     image = None if a.no_big else image_section(a, lcemd)
+    selfjoin = None if a.no_big else selfjoin_section(a, lcemd)
     big = None if a.no_big else big_workload(a, lcemd)
 
     out = {
@@ -459,6 +492,7 @@ def main():
         "precisions": precisions,
         "counters": counters,
         "image": image,
+        "selfjoin": selfjoin,
         "text_1M": big,
     }
     print(json.dumps(out))

@@ -197,6 +197,18 @@ int lcemd_check_histograms(const int64_t* rowptr, const int32_t* col, const floa
  * non-NULL also writes them (host int32, ascending). */
 int64_t lcemd_used_vocab(lcemd_ctx* ctx, int32_t* ids);
 
+/* Self-join (Sec. 5, the all-pairs protocol): the l nearest neighbours of
+ * every database histogram among the others (itself excluded), by the
+ * measure, direction and precision of `opts` (exclude_self must be -1).
+ * The D2Q matrix of the database against itself is formed once in device
+ * memory (n^2 float32, at most 64 GB); Q2D is its transpose and SYM the
+ * element-wise maximum of the two.  idx/dist: n * l entries, row b holding
+ * database row b's neighbours in ascending (distance, index) order; host
+ * arrays, or device arrays with flags = LCEMD_PTR_DEVICE (filled on the
+ * context's stream).  LCEMD_E_CAPACITY if n^2 floats exceed 64 GB. */
+int lcemd_selfjoin_topl(lcemd_ctx* ctx, const lcemd_opts* opts, int32_t l, uint32_t flags,
+                        int64_t* idx, float* dist);
+
 /* Per-kernel timing of the most recent lcemd_distances / lcemd_topl call
  * when enabled: device time measured with HIP events on the context's
  * stream.  lcemd_profile(ctx, 1) enables recording; lcemd_profile_get fills

@@ -343,7 +343,7 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
   int64_t q0 = 0;
   while (q0 < Q.B) {
     int64_t Bt = (int64_t)std::max<size_t>(1, c->table_budget / (per_q * 2 * zw_pairs(KT)));
-    Bt = std::min<int64_t>(Bt, 65535);
+    Bt = std::min<int64_t>(Bt, 16384);  // also bounds the rows a tile may need to redo
     const int64_t nq = std::min<int64_t>(Bt, Q.B - q0);
     float2* ZW;
     if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * c->v_used * 2 * zw_pairs(KT), ZW))) return rc;
@@ -891,6 +891,72 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
     HIPCHK(c, hipMemcpyAsync(S, dS, sizeof(int32_t) * total, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(Z, dZ, sizeof(float) * total, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(W, dW, sizeof(float) * total, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return finish_call(c);
+}
+
+// Self-join (Sec. 5's all-pairs protocol): every database histogram is a
+// query against all others, itself excluded.  The D2Q matrix of the
+// database against itself is computed once; its transpose is the Q2D
+// matrix, so the symmetric matrix is the element-wise maximum of the two.
+int lcemd_selfjoin_topl(lcemd_ctx* c, const lcemd_opts* o, int32_t l, uint32_t flags, int64_t* idx,
+                        float* dist) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  c->err.clear();
+  if ((rc = check_opts(c, o))) return rc;
+  if (o->exclude_self != -1) return fail(c, LCEMD_E_INVALID_ARG, "exclude_self must be -1 (the self-join excludes itself)");
+  if (!idx || !dist) return fail(c, LCEMD_E_INVALID_ARG, "idx/dist must not be NULL");
+  if (flags & ~LCEMD_PTR_DEVICE) return fail(c, LCEMD_E_INVALID_ARG, "unknown flags");
+  const int64_t n = c->n;
+  if (n < 2) return fail(c, LCEMD_E_INVALID_ARG, "the database needs at least 2 histograms");
+  if (l < 1 || l > LCEMD_MAX_L || l > n - 1)
+    return fail(c, LCEMD_E_INVALID_ARG, "need 1 <= l <= min(%d, n - 1)", LCEMD_MAX_L);
+  if ((double)n * (double)n * 4.0 > (double)(int64_t(64) << 30))
+    return fail(c, LCEMD_E_CAPACITY, "self-join of %lld histograms needs more than 64 GB", (long long)n);
+  (void)hipSetDevice(c->device);
+  prof_reset(c);
+  if ((rc = ensure_precision(c, o->precision))) return rc;
+  // the database as a device-resident query batch
+  QDev Q;
+  Q.B = n;
+  Q.nnz = c->nnz;
+  Q.ptr = c->xptr;
+  Q.col = c->xcol;
+  Q.hmax = c->db_hmax;
+  Q.device = true;
+  float* dval;
+  if ((rc = wsget(c, "db_val", (size_t)c->nnz, dval))) return rc;
+  HIPCHK(c, launch_record_weights(c->xcv, c->nnz, dval, c->stream));
+  Q.val = dval;
+  Q.hptr.resize(n + 1);
+  HIPCHK(c, hipMemcpyAsync(Q.hptr.data(), c->xptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float* D;
+  if ((rc = wsget(c, "selfjoin", (size_t)n * n, D))) return rc;
+  lcemd_opts od = *o;
+  od.direction = LCEMD_D2Q;
+  if ((rc = run_d2q(c, Q, &od, D, n))) return rc;
+  if (o->direction != LCEMD_D2Q) {
+    if ((rc = prof_begin(c, "square", (double)n * n * 8.0))) return rc;
+    HIPCHK(c, launch_square_pair(D, n, o->direction == LCEMD_SYM ? 1 : 0, c->stream));
+    if ((rc = prof_end(c))) return rc;
+  }
+  int64_t* didx = idx;
+  float* ddist = dist;
+  if (!(flags & LCEMD_PTR_DEVICE)) {
+    if ((rc = wsget(c, "topl_idx", (size_t)n * l, didx)) || (rc = wsget(c, "topl_dist", (size_t)n * l, ddist))) return rc;
+  }
+  uint64_t* cand;
+  if ((rc = wsget(c, "cand", (size_t)n * l, cand))) return rc;
+  if ((rc = prof_begin(c, "select", (double)n * n))) return rc;
+  if ((rc = select_rows(c, D, n, n, n, l, nullptr, 0, cand))) return rc;
+  if ((rc = prof_end(c))) return rc;
+  HIPCHK(c, launch_unpack_topl(cand, l, n, nullptr, l, didx, ddist, c->stream));
+  if (!(flags & LCEMD_PTR_DEVICE)) {
+    HIPCHK(c, hipMemcpyAsync(idx, didx, sizeof(int64_t) * n * l, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dist, ddist, sizeof(float) * n * l, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   return finish_call(c);

@@ -222,4 +222,63 @@ hipError_t launch_unpack_topl(const uint64_t* cand, int64_t cand_ld, int64_t row
   return hipGetLastError();
 }
 
+// The database weights (the second word of each 8-byte record).
+__global__ __launch_bounds__(kThreads) void k_record_weights(const int2* __restrict__ xcv, int64_t nnz,
+                                                             float* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < nnz) val[i] = __int_as_float(xcv[i].y);
+}
+
+hipError_t launch_record_weights(const int2* xcv, int64_t nnz, float* val, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_record_weights, dim3((unsigned)((nnz + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                     xcv, nnz, val);
+  return hipGetLastError();
+}
+
+// In-place n x n square matrix: mode 0 = transpose, 1 = symmetric maximum
+// (D[i][j] = D[j][i] = max of the two).  One workgroup per pair of 64x64
+// tiles (I <= J), both staged through LDS so reads and writes are coalesced.
+constexpr int kTT = 64;
+__global__ __launch_bounds__(kThreads) void k_square_pair(float* __restrict__ D, int64_t n, int mode) {
+  __shared__ float a[kTT][kTT + 1], b[kTT][kTT + 1];
+  const int64_t nt = (n + kTT - 1) / kTT;
+  // blockIdx -> (I, J), I <= J, row-major over the upper triangle of tiles
+  // rows 0..I-1 of the upper triangle hold I*nt - I(I-1)/2 tiles
+  const int64_t t = blockIdx.x;
+  auto before = [nt](int64_t r) { return r * nt - r * (r - 1) / 2; };
+  const double f = (double)(2 * nt + 1);
+  int64_t I = (int64_t)((f - sqrt(f * f - 8.0 * (double)t)) / 2.0);
+  I = I < 0 ? 0 : (I >= nt ? nt - 1 : I);
+  while (I > 0 && before(I) > t) --I;
+  while (I + 1 < nt && before(I + 1) <= t) ++I;
+  const int64_t J = I + (t - before(I));
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < kTT; r += kThreads / 64) {
+    const int64_t i = I * kTT + r, j = J * kTT + tx;
+    a[r][tx] = (i < n && j < n) ? D[i * n + j] : 0.f;
+    const int64_t i2 = J * kTT + r, j2 = I * kTT + tx;
+    b[r][tx] = (i2 < n && j2 < n) ? D[i2 * n + j2] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < kTT; r += kThreads / 64) {
+    // (I, J) tile gets the transpose of (J, I) (or the max with it), and back
+    const int64_t i = I * kTT + r, j = J * kTT + tx;
+    const float v1 = mode == 0 ? b[tx][r] : fmaxf(a[r][tx], b[tx][r]);
+    const int64_t i2 = J * kTT + r, j2 = I * kTT + tx;
+    const float v2 = mode == 0 ? a[tx][r] : fmaxf(b[r][tx], a[tx][r]);
+    if (i < n && j < n) D[i * n + j] = v1;
+    if (I != J && i2 < n && j2 < n) D[i2 * n + j2] = v2;
+  }
+}
+
+hipError_t launch_square_pair(float* D, int64_t n, int mode, hipStream_t s) {
+  const int64_t nt = (n + kTT - 1) / kTT;
+  const int64_t blocks = nt * (nt + 1) / 2;
+  if (n <= 0) return hipSuccess;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_square_pair, dim3((unsigned)blocks), dim3(kThreads), 0, s, D, n, mode);
+  return hipGetLastError();
+}
+
 }  // namespace lcemd

@@ -73,6 +73,8 @@ _SIGS = {
                              C.c_void_p, C.c_void_p]),
     "lcemd_tables": (C.c_int, [C.c_void_p, C.POINTER(lcemd_query), C.POINTER(lcemd_opts),
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lcemd_selfjoin_topl": (C.c_int, [C.c_void_p, C.POINTER(lcemd_opts), C.c_int32, C.c_uint32,
+                                      C.c_void_p, C.c_void_p]),
     "lcemd_used_vocab": (C.c_int64, [C.c_void_p, C.c_void_p]),
     "lcemd_profile": (C.c_int, [C.c_void_p, C.c_int]),
     "lcemd_counters": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -259,6 +261,25 @@ class Context:
             pi, pd = out[0].ctypes.data, out[1].ctypes.data
         self._check(self.lib.lcemd_topl(self.h, C.byref(q), C.byref(o), int(l), C.c_void_p(pi),
                                         C.c_void_p(pd)))
+        return out
+
+    def selfjoin_topl(self, l, method="act", k=1, direction="sym", precision="fp32", device=False,
+                      exclude_self=-1):
+        """Every database histogram against all others (itself excluded):
+        (idx, dist) of shape (n, l); torch tensors on the GPU if device."""
+        o = _opts(method, k, direction, precision, exclude_self)
+        if device:
+            import torch
+
+            out = (torch.empty((self.n, l), dtype=torch.int64, device="cuda"),
+                   torch.empty((self.n, l), dtype=torch.float32, device="cuda"))
+            pi, pd, fl = out[0].data_ptr(), out[1].data_ptr(), PTR_DEVICE
+            self._sync_stream(True)
+        else:
+            out = (np.empty((self.n, l), dtype=np.int64), np.empty((self.n, l), dtype=np.float32))
+            pi, pd, fl = out[0].ctypes.data, out[1].ctypes.data, 0
+        self._check(self.lib.lcemd_selfjoin_topl(self.h, C.byref(o), int(l), fl, C.c_void_p(pi),
+                                                 C.c_void_p(pd)))
         return out
 
     def tables(self, qptr, qcol, qval, k, precision="fp32"):

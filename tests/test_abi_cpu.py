@@ -25,7 +25,7 @@ def test_header_declares_expected_entry_points():
     for must in ("lcemd_create", "lcemd_destroy", "lcemd_load_embeddings", "lcemd_load_database",
                  "lcemd_distances", "lcemd_topl", "lcemd_tables", "lcemd_last_error",
                  "lcemd_server_start", "lcemd_server_submit", "lcemd_server_wait",
-                 "lcemd_server_stop", "lcemd_check_histograms"):
+                 "lcemd_server_stop", "lcemd_check_histograms", "lcemd_selfjoin_topl"):
         assert must in names
 
 
