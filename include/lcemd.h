@@ -96,7 +96,9 @@ extern "C" {
 #define LCEMD_L2_NORMALIZE 0x4u /* load_embeddings: scale rows to unit L2 norm */
 
 /* limits */
-#define LCEMD_MAX_HIST 512  /* max non-zeros of one query or database row */
+#define LCEMD_MAX_HIST 1024 /* max non-zeros of one query or database row (dense
+                               28x28 images with background: 784) */
+#define LCEMD_SERVE_MAX_HIST 512 /* serving: max words of a query or database row */
 #define LCEMD_MAX_L 1024    /* max l of lcemd_topl */
 #define LCEMD_MAX_K 512     /* max k of ACT */
 
@@ -133,9 +135,12 @@ int lcemd_create(lcemd_ctx** out, int device);
 /* Free all library-owned device memory and the context.  NULL-safe. */
 void lcemd_destroy(lcemd_ctx* ctx);
 
-/* Issue all further work of this context on `hip_stream` (a hipStream_t,
- * NULL = the library's own stream).  The caller keeps ownership. */
+/* Issue all further work of this context on `hip_stream` (a hipStream_t;
+ * NULL is HIP's null stream, not the library's own).  The caller keeps
+ * ownership.  Device-pointer calls are ordered on this stream only. */
 int lcemd_set_stream(lcemd_ctx* ctx, void* hip_stream);
+/* Go back to the context's own (non-blocking) stream. */
+int lcemd_use_own_stream(lcemd_ctx* ctx);
 
 /* Message of the last failing call on this context (context-owned string;
  * "" if none).  Also valid for ctx == NULL (then: last lcemd_create error). */
@@ -256,7 +261,7 @@ typedef struct {
   int32_t precision;       /* LCEMD_FP32, LCEMD_BF16 or LCEMD_FP8 */
   int32_t l;               /* neighbours returned per query, 1..min(LCEMD_MAX_L, n) */
   int32_t max_slots;       /* queries per batch (>= 1); lowered to fit memory_budget */
-  int32_t max_batch_words; /* words per batch (raised to LCEMD_MAX_HIST); 0 = no limit */
+  int32_t max_batch_words; /* words per batch (raised to LCEMD_SERVE_MAX_HIST); 0 = no limit */
   int64_t memory_budget;   /* device bytes for all lanes' buffers; 0 = 4 GiB */
   int32_t use_graph;       /* nonzero: two lanes, each batch replayed as a captured hipGraph
                               (while one runs, the other starts once max_slots/2 queries
@@ -265,13 +270,13 @@ typedef struct {
 } lcemd_server_cfg;
 
 /* Allocates every lane buffer up front.  LCEMD_E_CAPACITY if the budget
- * holds no query.  *out is NULL on
- * error. */
+ * holds no query or a database histogram has more than
+ * LCEMD_SERVE_MAX_HIST words.  *out is NULL on error. */
 int lcemd_server_start(lcemd_ctx* ctx, const lcemd_server_cfg* cfg, lcemd_server** out);
 /* Queue one query (host arrays of h words: ascending distinct ids < v,
  * weights >= 0 summing to 1; copied before return).  *ticket gets its id.
  * LCEMD_E_BAD_CSR for a malformed query, LCEMD_E_CAPACITY for h >
- * LCEMD_MAX_HIST.  Thread-safe. */
+ * LCEMD_SERVE_MAX_HIST.  Thread-safe. */
 int lcemd_server_submit(lcemd_server* s, const int32_t* col, const float* val, int32_t h,
                         uint64_t* ticket);
 /* Block until `ticket` completes; writes l (idx, dist) pairs in ascending

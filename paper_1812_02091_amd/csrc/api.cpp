@@ -264,7 +264,8 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
               int row_hmax) {
   // bf16 keys carry an exactness certificate only on the 128-row kernel;
   // deeper lists use float32 keys
-  if (prec != LCEMD_FP32 && (depth + kMargin > 32 || c->force_kernel || mode == P1_PAIR)) prec = LCEMD_FP32;
+  if (prec != LCEMD_FP32 && (depth + kMargin > 32 || c->force_kernel || mode == P1_PAIR || seg_hmax > kSegShort))
+    prec = LCEMD_FP32;
   if (!a.work_ctr) {
     int rc = wsget(c, "p1_counters", 8, a.work_ctr);
     if (rc) return rc;
@@ -278,7 +279,7 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
     const int KL = pow2ceil(depth + margin);
     a.KT_margin = margin;
     a.rb_max = (row_hmax + phase1_wide_rows() - 1) / phase1_wide_rows();
-    HIPCHK(c, launch_phase1_wide(a, mode, KL, prec, c->stream));
+    HIPCHK(c, launch_phase1_wide(a, mode, KL, prec, seg_hmax, c->stream));
   } else if (depth <= 64 && c->force_kernel != 2) {
     const int KL = pow2ceil(std::min(depth + margin, 64));
     a.KT_margin = margin;
@@ -287,6 +288,10 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
   } else {
     a.KT_margin = 0;
     a.rb_max = (row_hmax + kRows - 1) / kRows;
+    if (seg_hmax > kSegShort && !a.deep_keys) {
+      int rc = wsget(c, "deep_keys", (size_t)(kDeepSlots * kDeepSlotFloats), a.deep_keys);
+      if (rc) return rc;
+    }
     HIPCHK(c, launch_phase1_deep(a, mode, seg_hmax, PREC_F32, c->stream));
   }
   return LCEMD_OK;
@@ -527,7 +532,13 @@ void lcemd_destroy(lcemd_ctx* c) {
 
 int lcemd_set_stream(lcemd_ctx* c, void* s) {
   if (!c) return LCEMD_E_INVALID_ARG;
-  c->stream = s ? (hipStream_t)s : c->own_stream;
+  c->stream = (hipStream_t)s;
+  return LCEMD_OK;
+}
+
+int lcemd_use_own_stream(lcemd_ctx* c) {
+  if (!c) return LCEMD_E_INVALID_ARG;
+  c->stream = c->own_stream;
   return LCEMD_OK;
 }
 

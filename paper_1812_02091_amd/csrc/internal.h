@@ -19,6 +19,16 @@ constexpr int kKChunk = 32;      // phase-1 K (embedding dim) chunk staged in LD
 constexpr int kColChunk = 64;    // phase-1 columns per MFMA pass
 constexpr int kThreads = 256;    // threads per workgroup for every kernel
 constexpr int kSelectBuf = 2048; // LDS slots of the selection sort
+// Segments (the histogram whose words are a phase-1 workgroup's columns) of
+// up to kSegShort words keep their per-column arrays in LDS in every
+// phase-1 kernel variant; longer ones (up to LCEMD_MAX_HIST) run on float32
+// variants sized for them.
+constexpr int kSegShort = 512;
+// The keys kernel for segments longer than kSegShort keeps its rows of keys
+// in device memory: one region of kRows x (LCEMD_MAX_HIST + 4) floats per
+// workgroup of a launch, launches of at most kDeepSlots workgroups.
+constexpr int kDeepSlots = 2048;
+constexpr int64_t kDeepSlotFloats = (int64_t)kRows * (LCEMD_MAX_HIST + 4);
 
 // How a phase-1 workgroup finds its rows and its column segment, and what
 // it emits.
@@ -83,6 +93,10 @@ struct P1Args {
   // persistent kernels: eight work counters (one per XCD), zeroed by the
   // launcher on its stream before the kernel
   unsigned long long* work_ctr;
+  // keys kernel on segments longer than kSegShort: kDeepSlots regions of
+  // kDeepSlotFloats floats, and the first workgroup of the current launch
+  float* deep_keys;
+  int64_t blk0;
 };
 
 // Table layout of P1_TABLE: entry l of query qi's row for used word r.
@@ -116,7 +130,7 @@ __device__ __forceinline__ void zw_write_row(float2* ZW, int64_t zw_nq, int KT, 
 // kernel launchers (each in the translation unit of its kernel)
 hipError_t launch_phase1_deep(const P1Args& a, int mode, int hmax, int prec, hipStream_t s);
 hipError_t launch_phase1_fast(const P1Args& a, int mode, int KT, int prec, hipStream_t s);
-hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, hipStream_t s);
+hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, int seg_hmax, hipStream_t s);
 int phase1_wide_rows();
 hipError_t launch_fix_rows(const P1Args& a, int mode, int count, hipStream_t s);
 hipError_t launch_pair_reduce(const float* partial, int64_t npairs, int rb_max, float* out,

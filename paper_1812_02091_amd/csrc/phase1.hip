@@ -24,6 +24,8 @@
 //   mass the row can ever have to move (Lemma 1/2: a transfer never uses a
 //   destination past that point).  The last entry of a row is a sink with
 //   infinite capacity, which is Alg. 3's final "move the rest" step.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lcemd {
@@ -46,11 +48,15 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
 }
 
+// Rows of keys live in LDS for segments of up to kSegShort words; longer
+// segments (GKEYS) keep them in a device-memory region of the workgroup's
+// own (kDeepSlotFloats floats per workgroup of the launch).
 template <int MODE, int HMAX>
 struct P1Smem {
+  static constexpr bool GKEYS = HMAX > kSegShort;
   static constexpr int KS = HMAX + 4;        // key row stride (floats); KS % 64 == 4
   static constexpr int SS = kKChunk + 4;     // staging row stride (floats)
-  float keys[kRows * KS];
+  float keys[GKEYS ? 1 : kRows * KS];
   float Vs[kRows * SS];
   float Qs[kColChunk * SS];
   int cid[HMAX];
@@ -69,15 +75,35 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
   Sm& sm = *reinterpret_cast<Sm*>(smem_raw);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  static_assert(!Sm::GKEYS || Sm::KS * (int64_t)kRows <= kDeepSlotFloats, "key region too small");
 
   // ---------------- task decode ----------------
+  // (bx, by): (pair, row block) or (row block, query).  The device-memory
+  // key variant runs on a 1-D grid of at most kDeepSlots workgroups per
+  // launch, starting at workgroup a.blk0 of the whole task.
+  int64_t bx, by;
+  if constexpr (Sm::GKEYS) {
+    const int64_t t = a.blk0 + blockIdx.x;
+    if constexpr (MODE == P1_PAIR) {
+      bx = t / a.rb_max;
+      by = t % a.rb_max;
+    } else {
+      const int64_t nbx = (a.v_used + kRows - 1) / kRows;
+      bx = t % nbx;
+      by = t / nbx;
+    }
+  } else {
+    bx = blockIdx.x;
+    by = blockIdx.y;
+  }
+  float* const keys = Sm::GKEYS ? a.deep_keys + (int64_t)blockIdx.x * kRows * KS : sm.keys;
   int nrows = 0, h = 0;
   int64_t out_row0 = 0;  // first output table row (table modes)
   int64_t pidx = 0;
   int rb = 0;
   if constexpr (MODE == P1_PAIR) {
-    pidx = blockIdx.x;
-    rb = blockIdx.y;
+    pidx = bx;
+    rb = (int)by;
     int64_t b, u;
     if (a.cand) {
       const int64_t qi = pidx / a.cand_use, c = pidx % a.cand_use;
@@ -111,8 +137,8 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
       sm.qn[c] = a.vnorm[w];
     }
   } else {
-    const int64_t r0 = (int64_t)blockIdx.x * kRows;
-    const int64_t qi = blockIdx.y;
+    const int64_t r0 = bx * kRows;
+    const int64_t qi = by;
     const int64_t b = a.q0 + qi;
     nrows = (int)min((int64_t)kRows, a.v_used - r0);
     out_row0 = qi * a.v_used + r0;
@@ -180,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = wr + 8 * (r >> 2) + 4 * lh + (r & 3);
-        sm.keys[i * KS + c] = qc - 2.f * acc[r];
+        keys[i * KS + c] = qc - 2.f * acc[r];
       }
     }
   }
@@ -200,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
     else kef = min(a.k, h);
   }
   const float* vrow = a.V + (size_t)(done ? 0 : sm.rid[row]) * m_pad;
-  const float* krow = &sm.keys[row * KS];
+  const float* krow = &keys[row * KS];
   int depth = 0;
   float P = 0.f, rem = bound, cost = 0.f;
   uint64_t last = 0;
@@ -296,6 +322,22 @@ static hipError_t launch_one(const P1Args& a, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)k_phase1_f32<MODE, HMAX>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
+  if constexpr (P1Smem<MODE, HMAX>::GKEYS) {
+    // launches of at most kDeepSlots workgroups, one key region each; the
+    // launches of a stream run one after another, so regions are reused
+    if (!a.deep_keys) return hipErrorInvalidValue;
+    const int64_t total = MODE == P1_PAIR ? a.npairs * (int64_t)a.rb_max
+                                          : (a.v_used + kRows - 1) / kRows * a.nq;
+    for (int64_t b0 = 0; b0 < total; b0 += kDeepSlots) {
+      P1Args c = a;
+      c.blk0 = b0;
+      const unsigned g = (unsigned)std::min<int64_t>(kDeepSlots, total - b0);
+      hipLaunchKernelGGL((k_phase1_f32<MODE, HMAX>), dim3(g), dim3(kThreads), shmem, s, c);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   dim3 grid;
   if (MODE == P1_PAIR) {
     grid = dim3((unsigned)a.npairs, (unsigned)a.rb_max, 1);
@@ -311,6 +353,7 @@ static hipError_t launch_mode(const P1Args& a, int hmax, hipStream_t s) {
   if (hmax <= 128) return launch_one<MODE, 128>(a, s);
   if (hmax <= 256) return launch_one<MODE, 256>(a, s);
   if (hmax <= 512) return launch_one<MODE, 512>(a, s);
+  if (hmax <= LCEMD_MAX_HIST) return launch_one<MODE, LCEMD_MAX_HIST>(a, s);
   return hipErrorInvalidValue;
 }
 

@@ -42,7 +42,8 @@ constexpr int kWC = 128;        // columns per MFMA pass
 constexpr int kStride = 144;    // bytes per staged column slice (128 + 16 pad)
 constexpr int kCK = 66;         // floats per key row (64 columns + 2 pad)
 constexpr int kQSCap = kWR * kCK;  // floats of the staging area (the key buffer's size)
-constexpr int kSeg = LCEMD_MAX_HIST;
+constexpr int kSeg = kSegShort;            // segment words held in LDS (short variant)
+constexpr int kSegLong = LCEMD_MAX_HIST;   // long variant (float32 keys)
 constexpr int kGroupW = 8;      // queries per tile group (table modes)
 constexpr float kGuardW = 0.25f;
 constexpr float kBandBF16 = 0.015625f * 1.07f;  // 2^-6 * 1.07
@@ -74,28 +75,33 @@ __device__ __forceinline__ uint64_t w_shfl1(uint64_t v) {
 }
 
 // Selection keys.  Exact keys: (order-preserving key bits, position) in 64
-// bits (float32 pair mode).  Quantised keys (the table modes): the key's 9
-// low bits give way to the position (positions < 512), one 32-bit word,
-// rounded down in value by at most 2^-14 of the key's magnitude; lists keep
-// every entry within that band past their cut and are re-sorted afterwards
-// by the exact keys (float32: the contraction's key, kept beside the list;
-// bf16/fp8: the recomputed distances).
-template <bool QK>
+// bits (float32 pair mode).  Quantised keys (the table modes): the key's PB
+// low bits give way to the position (9 bits for segments of up to 512
+// words, 10 up to 1024), one 32-bit word, rounded down in value by at most
+// 2^(PB-23) of the key's magnitude; lists keep every entry within twice
+// that band past their cut and are re-sorted afterwards by the exact keys
+// (float32: the contraction's key, kept beside the list; bf16/fp8: the
+// recomputed distances).
+template <bool QK, int PB = 9>
 struct KeyOps {
   using T = uint32_t;
   static constexpr T kNone = 0xffffffffu;
-  __device__ static T pack(float f, uint32_t pos) { return (w_bits(f) & 0xfffffe00u) | pos; }
+  static constexpr uint32_t kPos = (1u << PB) - 1u;
+  // twice the largest relative rounding of a key, 2 * 2^(PB-23)
+  static constexpr float kRound = (float)(1u << PB) / (float)(1u << 22);
+  __device__ static T pack(float f, uint32_t pos) { return (w_bits(f) & ~kPos) | pos; }
   __device__ static float key(T k) {
-    const uint32_t o = k & 0xfffffe00u;
+    const uint32_t o = k & ~kPos;
     return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
   }
-  __device__ static uint32_t pos(T k) { return k & 0x1ffu; }
+  __device__ static uint32_t pos(T k) { return k & kPos; }
   __device__ static T shfl1(T v) { return (T)__shfl_xor((int)v, 1); }
 };
-template <>
-struct KeyOps<false> {
+template <int PB>
+struct KeyOps<false, PB> {
   using T = uint64_t;
   static constexpr T kNone = ~0ull;
+  static constexpr float kRound = 0.f;  // exact keys
   __device__ static T pack(float f, uint32_t pos) { return w_pack(f, pos); }
   __device__ static float key(T k) { return w_unpack(k); }
   __device__ static uint32_t pos(T k) { return (uint32_t)k; }
@@ -199,7 +205,7 @@ __device__ __forceinline__ void slice_mfma(int ntile, floatx16 (&acc)[4], const 
   }
 }
 
-template <int KL, int PREC, bool QK, bool EX>
+template <int KL, int PREC, bool QK, bool EX, int SEG = kSeg>
 struct WideSmem {
   static constexpr int KLS = KL + 1 + (EX ? 1 : 0);  // list row stride (odd or +1: spreads rows over banks)
   union {
@@ -210,9 +216,9 @@ struct WideSmem {
   } u;
   typename KeyOps<QK>::T lst[2][kWR * KLS];
   float lkx[EX ? 2 : 1][EX ? kWR * KLS : 1];  // float32 quantised keys: the exact keys beside the list
-  int cid[kSeg];
-  float cap[kSeg];
-  float qn[kSeg];
+  int cid[SEG];
+  float cap[SEG];
+  float qn[SEG];
   int rid[kWR];
   float rbound[kWR];
   float rvn[kWR];
@@ -222,7 +228,7 @@ struct WideSmem {
   int rcut[kWR];     // the last merge reached k_eff or the row's bound
   float qmax;
   float rsc[PREC == PREC_FP8 ? kWR : 1];   // fp8 row scales
-  float csc[PREC == PREC_FP8 ? kSeg : 1];  // fp8 column scales
+  float csc[PREC == PREC_FP8 ? SEG : 1];  // fp8 column scales
 };
 
 // Float32 dot products <v_row, c_pos> of a thread's listed candidates
@@ -270,14 +276,17 @@ __device__ __forceinline__ void wide_dots(float (&ex)[KH], const int (&ps)[KH], 
 
 // One work item: (query, 128-row block) in the table modes, (pair, row
 // block) in pair mode.  Returns early (uniformly) for empty items.
-template <int MODE, int KL, int PREC>
+template <int MODE, int KL, int PREC, bool LONG>
 __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_raw, int64_t item) {
   // quantised keys everywhere but in the float32 pair mode; EX: float32
-  // with quantised keys keeps the exact keys and one more list slot
+  // with quantised keys keeps the exact keys and one more list slot.
+  // LONG: segments of up to kSegLong words (float32 only, 10 position bits)
+  static_assert(!LONG || PREC == PREC_F32, "long segments run with float32 keys");
   constexpr bool QK = PREC != PREC_F32 || MODE != P1_PAIR;
   constexpr bool EX = PREC == PREC_F32 && QK;
   constexpr int KLC = KL + (EX ? 1 : 0);  // list capacity
-  using Sm = WideSmem<KL, PREC, QK, EX>;
+  constexpr int PB = LONG ? 10 : 9;
+  using Sm = WideSmem<KL, PREC, QK, EX, LONG ? kSegLong : kSeg>;
   constexpr int KLS = Sm::KLS;
   Sm& sm = *reinterpret_cast<Sm*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -476,7 +485,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       __syncthreads();
       // this thread's 32 contiguous columns, read without branches (the
       // buffer is fully allocated; columns past h are masked afterwards)
-      using KO = KeyOps<QK>;
+      using KO = KeyOps<QK, PB>;
       using KT_ = typename KO::T;
       KT_ kk[32];
       const float2* krow = (const float2*)&sm.u.ck[row * kCK + 32 * sub];
@@ -497,7 +506,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       // approximate keys: the error band plus the rounding of 32-bit keys
       const float band = !QK ? 0.f
                              : band_coef<PREC>() * sqrtf(sm.rvn[row]) * sm.qmax +
-                                   1.2207e-4f * (sm.qmax * sm.qmax + 2.f * sqrtf(sm.rvn[row]) * sm.qmax);
+                                   KO::kRound * (sm.qmax * sm.qmax + 2.f * sqrtf(sm.rvn[row]) * sm.qmax);
       int ptr = 0, w = 0;
       float P = 0.f, K0 = 0.f;
       bool cut = false;
@@ -560,8 +569,8 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
   if constexpr (PREC == PREC_F32) {
     for (int l = sub; l < len; l += 2) {
       const auto e = L[l];
-      const int pos = (int)KeyOps<QK>::pos(e);
-      float d2 = sm.rvn[row] + (EX ? sm.lkx[EX ? par : 0][EX ? row * KLS + l : 0] : KeyOps<QK>::key(e));
+      const int pos = (int)KeyOps<QK, PB>::pos(e);
+      float d2 = sm.rvn[row] + (EX ? sm.lkx[EX ? par : 0][EX ? row * KLS + l : 0] : KeyOps<QK, PB>::key(e));
       bool need = !(d2 >= kGuardW * (sm.rvn[row] + sm.qn[pos]));
       if (MODE != P1_TABLE_FULL && a.method == LCEMD_OMR && l == 0) need = true;
       if (need) d2 = w_exact_d2(a.V, a.m_pad, sm.rid[row], sm.cid[pos]);
@@ -575,7 +584,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     for (int e = 0; e < KH; ++e) {
       ex[e] = 0.f;
       const int l = sub + 2 * e;
-      ps[e] = l < len ? (int)KeyOps<QK>::pos(L[l]) : 0;
+      ps[e] = l < len ? (int)KeyOps<QK, PB>::pos(L[l]) : 0;
     }
     const float* vr = a.V + (size_t)sm.rid[row] * a.m_pad;
     // chunks of D dims of all h segment vectors per LDS pass, as wide as
@@ -615,7 +624,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     if constexpr (EX) {
       // exact re-sort by (contraction key, position), distances moving
       // along; the list then holds positions
-      for (int i = 0; i < len; ++i) Lw[i] = KeyOps<QK>::pos(Lw[i]);
+      for (int i = 0; i < len; ++i) Lw[i] = KeyOps<QK, PB>::pos(Lw[i]);
       for (int i = 1; i < len; ++i) {
         const uint64_t e = w_pack(Lx[i], (uint32_t)Lw[i]);
         const float z = Z2[i];
@@ -633,7 +642,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     } else if constexpr (PREC != PREC_F32) {
       // exact re-sort by (squared distance, position); the list then holds
       // positions
-      for (int i = 0; i < len; ++i) Lw[i] = KeyOps<QK>::pos(Lw[i]);
+      for (int i = 0; i < len; ++i) Lw[i] = KeyOps<QK, PB>::pos(Lw[i]);
       for (int i = 1; i < len; ++i) {
         const uint64_t e = w_pack(Z2[i], (uint32_t)Lw[i]);
         int j = i - 1;
@@ -730,7 +739,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
 // from the counter of its XCD (workgroup i runs on XCD i % 8), which walks a
 // contiguous eighth of the items.  No workgroup waits on another; each
 // exits once its counter passes the end of its range.
-template <int MODE, int KL, int PREC>
+template <int MODE, int KL, int PREC, bool LONG>
 __global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a, int64_t total) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int64_t s_item;
@@ -742,15 +751,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a, int64_t t
     __syncthreads();
     const int64_t item = s_item;
     if (item >= hi) break;
-    wide_task<MODE, KL, PREC>(a, smem_raw, item);
+    wide_task<MODE, KL, PREC, LONG>(a, smem_raw, item);
   }
 }
 
-template <int MODE, int KL, int PREC>
+template <int MODE, int KL, int PREC, bool LONG>
 static hipError_t launch_wide_one(const P1Args& a, hipStream_t s) {
   constexpr bool QK = PREC != PREC_F32 || MODE != P1_PAIR;
-  const size_t shmem = sizeof(WideSmem<KL, PREC, QK, PREC == PREC_F32 && QK>);
-  const void* fn = (const void*)k_phase1_wide<MODE, KL, PREC>;
+  const size_t shmem = sizeof(WideSmem<KL, PREC, QK, PREC == PREC_F32 && QK, LONG ? kSegLong : kSeg>);
+  const void* fn = (const void*)k_phase1_wide<MODE, KL, PREC, LONG>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   int64_t total;
@@ -766,26 +775,26 @@ static hipError_t launch_wide_one(const P1Args& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int grid = persistent_grid(fn, kThreads, shmem, total);
   if (grid <= 0) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_phase1_wide<MODE, KL, PREC>), dim3(grid), dim3(kThreads), shmem, s, a, total);
+  hipLaunchKernelGGL((k_phase1_wide<MODE, KL, PREC, LONG>), dim3(grid), dim3(kThreads), shmem, s, a, total);
   return hipGetLastError();
 }
 
-template <int MODE, int PREC>
+template <int MODE, int PREC, bool LONG>
 static hipError_t launch_wide_mode(const P1Args& a, int KL, hipStream_t s) {
-  if (KL <= 2) return launch_wide_one<MODE, 2, PREC>(a, s);
-  if (KL <= 4) return launch_wide_one<MODE, 4, PREC>(a, s);
-  if (KL <= 8) return launch_wide_one<MODE, 8, PREC>(a, s);
-  if (KL <= 16) return launch_wide_one<MODE, 16, PREC>(a, s);
-  if (KL <= 32) return launch_wide_one<MODE, 32, PREC>(a, s);
+  if (KL <= 2) return launch_wide_one<MODE, 2, PREC, LONG>(a, s);
+  if (KL <= 4) return launch_wide_one<MODE, 4, PREC, LONG>(a, s);
+  if (KL <= 8) return launch_wide_one<MODE, 8, PREC, LONG>(a, s);
+  if (KL <= 16) return launch_wide_one<MODE, 16, PREC, LONG>(a, s);
+  if (KL <= 32) return launch_wide_one<MODE, 32, PREC, LONG>(a, s);
   return hipErrorInvalidValue;
 }
 
-template <int PREC>
+template <int PREC, bool LONG = false>
 static hipError_t launch_wide_prec(const P1Args& a, int mode, int KL, hipStream_t s) {
   switch (mode) {
-    case P1_TABLE: return launch_wide_mode<P1_TABLE, PREC>(a, KL, s);
-    case P1_TABLE_FULL: return launch_wide_mode<P1_TABLE_FULL, PREC>(a, KL, s);
-    case P1_PAIR: return launch_wide_mode<P1_PAIR, PREC>(a, KL, s);
+    case P1_TABLE: return launch_wide_mode<P1_TABLE, PREC, LONG>(a, KL, s);
+    case P1_TABLE_FULL: return launch_wide_mode<P1_TABLE_FULL, PREC, LONG>(a, KL, s);
+    case P1_PAIR: return launch_wide_mode<P1_PAIR, PREC, LONG>(a, KL, s);
   }
   return hipErrorInvalidValue;
 }
@@ -799,7 +808,7 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
   const int count = min(*a.fix_count, a.fix_cap);
   for (int item = blockIdx.x; item < count; item += gridDim.x) {
   __shared__ float vrow[4096];
-  __shared__ uint64_t keys[kSeg];
+  __shared__ uint64_t keys[kSegLong];
   const int tid = threadIdx.x;
   const int64_t flat = list[item];
   const int64_t qi = flat / a.v_used, r = flat % a.v_used;
@@ -809,7 +818,7 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
   const int vid = a.used[r];
   for (int d = tid; d < a.m_pad; d += kThreads) vrow[d] = a.V[(size_t)vid * a.m_pad + d];
   __syncthreads();
-  for (int c = tid; c < kSeg; c += kThreads) {
+  for (int c = tid; c < kSegLong; c += kThreads) {
     uint64_t kk = ~0ull;
     if (c < h) {
       const float4* q = (const float4*)(a.V + (size_t)a.qcol[s0 + c] * a.m_pad);
@@ -827,9 +836,9 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
     keys[c] = kk;
   }
   __syncthreads();
-  for (int k = 2; k <= kSeg; k <<= 1) {
+  for (int k = 2; k <= kSegLong; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < kSeg / 2; i += kThreads) {
+      for (int i = tid; i < kSegLong / 2; i += kThreads) {
         const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
         const int hi = lo + j;
         const bool asc = (lo & k) == 0;
@@ -904,7 +913,9 @@ hipError_t launch_fix_rows(const P1Args& a, int mode, int count, hipStream_t s) 
 
 int phase1_wide_rows() { return kWR; }
 
-hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, hipStream_t s) {
+hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, int seg_hmax, hipStream_t s) {
+  if (seg_hmax > kSegLong) return hipErrorInvalidValue;
+  if (seg_hmax > kSeg) return prec == PREC_F32 ? launch_wide_prec<PREC_F32, true>(a, mode, KL, s) : hipErrorInvalidValue;
   if (prec == PREC_F32) return launch_wide_prec<PREC_F32>(a, mode, KL, s);
   if (prec == PREC_BF16) {
     if (!a.Vb) return hipErrorInvalidValue;

@@ -98,7 +98,7 @@ struct lcemd_server {
   lcemd_server_cfg cfg{};
   int prec = LCEMD_FP32;
   int KT = 1, depth_pair = 1, use = 0, cld = 0, l = 0;
-  int B = 1, W = LCEMD_MAX_HIST;
+  int B = 1, W = LCEMD_SERVE_MAX_HIST;
   bool continuous = true;
   std::vector<Lane> lanes;
   std::thread worker;
@@ -188,7 +188,7 @@ int issue(lcemd_server* s, Lane& L) {
     a.fix_count = L.ints + 9;
     a.fix_list = L.fixl;
     a.fix_cap = kFixCapLane;
-    if ((rc = p1_launch(c, a, P1_TABLE, s->prec, s->KT, LCEMD_MAX_HIST, LCEMD_MAX_HIST))) break;
+    if ((rc = p1_launch(c, a, P1_TABLE, s->prec, s->KT, LCEMD_SERVE_MAX_HIST, LCEMD_SERVE_MAX_HIST))) break;
     HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
     HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, L.ZW, zw_pitch(s->B), s->KT, s->B, L.nq,
                                        L.d2q, c->n, L.ctr + 8, L.stream));
@@ -203,7 +203,7 @@ int issue(lcemd_server* s, Lane& L) {
     p.cand_use = s->use;
     p.npairs = (int64_t)s->B * s->use;
     p.partial = L.partial;
-    if ((rc = p1_launch(c, p, P1_PAIR, LCEMD_FP32, s->depth_pair, c->db_hmax, LCEMD_MAX_HIST))) break;
+    if ((rc = p1_launch(c, p, P1_PAIR, LCEMD_FP32, s->depth_pair, c->db_hmax, LCEMD_SERVE_MAX_HIST))) break;
     HIPCHK(c, launch_pair_reduce(L.partial, p.npairs, p.rb_max, L.q2dv, s->use, s->use, L.stream));
     HIPCHK(c, launch_finalize_sym(L.cand, s->cld, s->use, L.q2dv, s->B, nullptr, c->n, s->l, L.idx,
                                   L.dist, L.flags, L.stream));
@@ -215,7 +215,7 @@ int setup_lane(lcemd_server* s, Lane& L) {
   lcemd_ctx* c = s->ctx;
   int rc;
   const size_t B = s->B, W = s->W, n = c->n;
-  const int rbcap = (LCEMD_MAX_HIST + kRows - 1) / kRows;
+  const int rbcap = (LCEMD_SERVE_MAX_HIST + kRows - 1) / kRows;
   HIPCHK(c, hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
   HIPCHK(c, hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
   if ((rc = dalloc(c, L.qptr, B + 1, "lane")) || (rc = dalloc(c, L.qcol, W, "lane")) ||
@@ -419,6 +419,9 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   if (cfg->max_slots < 1) return fail(c, LCEMD_E_INVALID_ARG, "max_slots must be >= 1");
   for (int i = 0; i < 5; ++i)
     if (cfg->reserved[i]) return fail(c, LCEMD_E_INVALID_ARG, "reserved fields must be 0");
+  if (c->db_hmax > LCEMD_SERVE_MAX_HIST)
+    return fail(c, LCEMD_E_CAPACITY, "serving needs database histograms of at most %d words (longest: %d)",
+                LCEMD_SERVE_MAX_HIST, c->db_hmax);
   (void)hipSetDevice(c->device);
   int rc = ensure_precision(c, cfg->precision);
   if (rc) return rc;
@@ -429,7 +432,7 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   s->cfg = *cfg;
   s->prec = cfg->precision;
   s->l = cfg->l;
-  s->KT = method_depth(cfg->method, cfg->k, LCEMD_MAX_HIST);
+  s->KT = method_depth(cfg->method, cfg->k, LCEMD_SERVE_MAX_HIST);
   s->depth_pair = method_depth(cfg->method, cfg->k, c->db_hmax);
   s->use = (int)std::min<int64_t>(std::max(4 * cfg->l, 64), c->n);
   s->cld = s->use < c->n ? s->use + 1 : s->use;
@@ -438,7 +441,7 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   const int nlanes = cfg->use_graph ? 2 : 1;
   s->continuous = nlanes > 1;
   const double per_q = (double)c->v_used * zw_pairs(s->KT) * 16 + (double)c->n * 4 + (double)s->cld * 8 +
-                       (double)s->use * 4 * (1 + (LCEMD_MAX_HIST + kRows - 1) / kRows) + 64.0 * s->l;
+                       (double)s->use * 4 * (1 + (LCEMD_SERVE_MAX_HIST + kRows - 1) / kRows) + 64.0 * s->l;
   const int64_t budget = cfg->memory_budget > 0 ? cfg->memory_budget : (int64_t(4) << 30);
   const int64_t fit = (int64_t)(budget / (per_q * nlanes));
   if (fit < 1) {
@@ -447,8 +450,8 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
                 (long long)budget, per_q);
   }
   s->B = (int)std::min<int64_t>(cfg->max_slots, fit);
-  s->W = cfg->max_batch_words > 0 ? std::max(cfg->max_batch_words, (int32_t)LCEMD_MAX_HIST)
-                                   : s->B * LCEMD_MAX_HIST;
+  s->W = cfg->max_batch_words > 0 ? std::max(cfg->max_batch_words, (int32_t)LCEMD_SERVE_MAX_HIST)
+                                   : s->B * LCEMD_SERVE_MAX_HIST;
   s->lanes.resize(nlanes);
   for (Lane& L : s->lanes) {
     if ((rc = setup_lane(s, L))) {
@@ -466,7 +469,7 @@ int lcemd_server_submit(lcemd_server* s, const int32_t* col, const float* val, i
                         uint64_t* ticket) {
   if (!s || !col || !val || !ticket) return LCEMD_E_INVALID_ARG;
   if (h < 1) return LCEMD_E_BAD_CSR;
-  if (h > LCEMD_MAX_HIST) return LCEMD_E_CAPACITY;
+  if (h > LCEMD_SERVE_MAX_HIST) return LCEMD_E_CAPACITY;
   int64_t ptr[2] = {0, h};
   lcemd_ctx scratch;
   int hm = 0;

@@ -21,7 +21,8 @@ RWMD, OMR, ACT, ICT = 0, 1, 2, 3
 D2Q, Q2D, SYM = 0, 1, 2
 FP32, BF16, FP8 = 0, 1, 2
 PTR_DEVICE, NORMALIZE, L2_NORMALIZE = 0x1, 0x2, 0x4
-MAX_HIST, MAX_L, MAX_K = 512, 1024, 512
+MAX_HIST, MAX_L, MAX_K = 1024, 1024, 512
+SERVE_MAX_HIST = 512
 
 METHOD = {"rwmd": RWMD, "omr": OMR, "act": ACT, "ict": ICT}
 DIRECTION = {"d2q": D2Q, "q2d": Q2D, "sym": SYM}
@@ -63,6 +64,7 @@ _SIGS = {
     "lcemd_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
     "lcemd_destroy": (None, [C.c_void_p]),
     "lcemd_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lcemd_use_own_stream": (C.c_int, [C.c_void_p]),
     "lcemd_last_error": (C.c_char_p, [C.c_void_p]),
     "lcemd_load_embeddings": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_uint32]),
     "lcemd_load_database": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -188,7 +190,7 @@ class Context:
 
             self._check(self.lib.lcemd_set_stream(self.h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
         else:
-            self._check(self.lib.lcemd_set_stream(self.h, None))
+            self._check(self.lib.lcemd_use_own_stream(self.h))
 
     # ---- loads ----
     def load_embeddings(self, V, l2_normalize: bool = False):

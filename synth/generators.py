@@ -22,6 +22,9 @@ from typing import Callable, Dict, Optional
 import numpy as np
 
 STREAM_V, STREAM_DB, STREAM_Q, STREAM_SAMPLE, STREAM_ARRIVAL = 0, 1, 2, 3, 4
+# background pixel value of the dense image workload, on the scale where a
+# disc pixel's intensity is in (0, 1]: one grey level of an 8-bit image
+BACKGROUND = 1.0 / 255.0
 
 
 @dataclass
@@ -224,10 +227,15 @@ def zipf_histograms(rng, n: int, v: int, s: float, length_fn: Callable, weight: 
     return CSR(rowptr, cols, _normalise_rows(rowptr, raw))
 
 
-def blob_histograms(rng, n: int, side: int = 28, rmin: int = 4, rmax: int = 10, chunk: int = 8192) -> CSR:
+def blob_histograms(rng, n: int, side: int = 28, rmin: int = 4, rmax: int = 10, chunk: int = 8192,
+                    background: float = 0.0) -> CSR:
     """n greyscale 'blob' images: radius ~ U{rmin..rmax}, centre ~
     U{r..side-1-r}^2, pixels inside the disc get intensity 1 - U[0,1);
-    L1-normalised (pixel weights = normalised pixel values, Sec. 5)."""
+    L1-normalised (pixel weights = normalised pixel values, Sec. 5).
+
+    background > 0: every pixel is a coordinate (Sec. 5, images with their
+    background): each pixel's value is background + its disc intensity, so
+    all side*side pixels carry weight (the same random draws as without)."""
     yy, xx = np.divmod(np.arange(side * side), side)
     ptrs, cols_l, raws = [np.zeros(1, dtype=np.int64)], [], []
     base = 0
@@ -239,8 +247,15 @@ def blob_histograms(rng, n: int, side: int = 28, rmin: int = 4, rmax: int = 10, 
         mask = (yy[None, :] - cy[:, None]) ** 2 + (xx[None, :] - cx[:, None]) ** 2 <= (r[:, None] ** 2)
         rows, px = np.nonzero(mask)
         lens = mask.sum(1)
+        raw = 1.0 - rng.random(px.shape[0])
+        if background > 0:
+            dense = np.full((c, side * side), float(background))
+            dense[rows, px] += raw
+            lens = np.full(c, side * side, dtype=np.int64)
+            px = np.tile(np.arange(side * side), c)
+            raw = dense.ravel()
         cols_l.append(px.astype(np.int32))
-        raws.append(1.0 - rng.random(px.shape[0]))
+        raws.append(raw)
         ptrs.append(base + np.cumsum(lens))
         base += int(lens.sum())
     rowptr = np.concatenate(ptrs).astype(np.int64)
@@ -262,7 +277,7 @@ def _rng(config: int, stream: int):
 
 
 # --------------------------------------------------------------------------
-# the five workloads
+# the workloads
 # --------------------------------------------------------------------------
 def _tiny(n=200, B=8, v=2000, m=64, **_):
     V = gaussian_embeddings(_rng(1, STREAM_V), v, m, unit=False)
@@ -291,6 +306,14 @@ def _image(n=60000, B=10000, **_):
                     meta=dict(config=3, v=784, m=2, n=n, B=B))
 
 
+def _image_bg(n=60000, B=10000, **_):
+    V = grid_embeddings(28)
+    db = blob_histograms(_rng(5, STREAM_DB), n, background=BACKGROUND)
+    q = blob_histograms(_rng(5, STREAM_Q), B, background=BACKGROUND)
+    return Workload("image-bg", V, db, q, ks=(1, 2, 4, 16), ell=16,
+                    meta=dict(config=5, v=784, m=2, n=n, B=B, background=BACKGROUND))
+
+
 def _precision(n=1_000_000, B=4096, v=1_000_000, m=300, **_):
     return _text(n=n, B=B, v=v, m=m, cfg=4)
 
@@ -300,6 +323,7 @@ WORKLOADS = {
     "text": _text,        # 70,000 x 300 unit; 18,000 docs ~120 words; 1,000 queries
     "image": _image,      # 28x28 grid; 60,000 blobs; 10,000 queries
     "text-1M": _precision,  # 1e6 x 300 unit; 1e6 docs; 4,096 queries
+    "image-bg": _image_bg,  # 28x28 grid, every pixel a coordinate; 60,000 x 10,000
 }
 
 

@@ -49,6 +49,7 @@ def test_header_constants_match_binding():
     assert const("LCEMD_ICT") == L.ICT and const("LCEMD_SYM") == L.SYM
     assert const("LCEMD_PTR_DEVICE") == L.PTR_DEVICE
     assert const("LCEMD_MAX_HIST") == L.MAX_HIST and const("LCEMD_MAX_L") == L.MAX_L
+    assert const("LCEMD_SERVE_MAX_HIST") == L.SERVE_MAX_HIST
 
 
 def _has_gpu():

@@ -348,3 +348,32 @@ def test_cost_matrix_is_euclidean_not_squared():
     assert C[0, 0] == 5.0 and R[0, 0] == 25.0 and C[1, 1] == 0.0
     C1, _ = O.cost_matrix(np.array([[0.0], [1.0]]), np.array([[0.0], [3.0]]))
     assert np.array_equal(C1, _c1d([0, 1], [0, 3]))
+
+
+def test_dense_background_images_closed_forms():
+    """Images with their background (every one of the 28x28 pixels is a
+    coordinate of every histogram, Sec. 5): RWMD is exactly 0 both ways; each
+    pixel's nearest other pixel is at distance 1, so OMR (Alg. 1) and ACT(2)
+    (Alg. 3) keep min(p_i, q_i) in place and move the rest one grid step:
+    both equal sum_i max(p_i - q_i, 0) for source p (the total variation
+    distance when both sum to 1).  Deeper measures grow along Thm 2's
+    chain."""
+    from synth import make_workload
+
+    w = make_workload("image-bg", n=3, B=2)
+    assert np.all(np.diff(w.db.rowptr) == 784) and np.all(np.diff(w.queries.rowptr) == 784)
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    for b in range(2):
+        c, qv = w.queries.row(b)
+        for d in ("d2q", "q2d"):
+            assert np.all(orc.row_distances(c, qv, "rwmd", 1, d) == 0.0)
+            omr = orc.row_distances(c, qv, "omr", 1, d)
+            act2 = orc.row_distances(c, qv, "act", 2, d)
+            q64 = qv.astype(np.float64)
+            src = [(w.db.row(u)[1].astype(np.float64), q64) for u in range(3)]
+            tv = np.array([np.maximum(a - b, 0).sum() if d == "d2q" else np.maximum(b - a, 0).sum()
+                           for a, b in src])
+            assert np.allclose(omr, tv, rtol=1e-12, atol=0) and np.allclose(act2, tv, rtol=1e-12, atol=0)
+            act4 = orc.row_distances(c, qv, "act", 4, d)
+            ict = orc.row_distances(c, qv, "ict", 1, d)
+            assert np.all(tv > 0) and np.all(act2 <= act4 + 1e-12) and np.all(act4 <= ict + 1e-12)
