@@ -224,6 +224,44 @@ def selfjoin_section(a, lcemd):
     return res
 
 
+def dense_section(a, lcemd):
+    """Images with their background (every one of the 784 pixels a
+    coordinate, Sec. 5): 60,000 database histograms of 784 words, symmetric
+    top-16 for RWMD, OMR, ACT k=2, k=16 and ICT.  RWMD is 0 for every pair
+    here; the ACT family separates the images."""
+    import torch
+
+    from synth import make_workload
+
+    w = make_workload("image-bg", B=1000)
+    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
+    n = w.db.n
+    dev = torch.device("cuda:0")
+    res = {"workload": f"image-bg: 784 pixels x 2 coordinates, {n} database histograms of 784 words "
+                       f"({w.db.nnz} non-zeros), symmetric top-16"}
+    for method, k, B in (("rwmd", 1, 1000), ("omr", 1, 1000), ("act", 2, 1000), ("act", 16, 1000),
+                         ("ict", 1, 100)):
+        qs = w.queries.take(list(range(B)))
+        q = [torch.from_numpy(x).to(dev) for x in (qs.rowptr, qs.col, qs.val)]
+        small = w.queries.take([0, 1])
+        ctx.topl(small.rowptr, small.col, small.val, 16, method=method, k=k, direction="sym")
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        idx, dist = ctx.topl(*q, 16, method=method, k=k, direction="sym")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ph = {p["name"]: p["ms"] for p in ctx.profile_get()}
+        ctx.profile(False)
+        rec = {"queries": B, "seconds": dt, "distances_per_s": B * n / dt, "phase_ms": ph}
+        if method == "rwmd":
+            rec["all_zero"] = bool((dist == 0).all())
+        res[f"{method}{k}" if method == "act" else method] = rec
+        print(f"[bench] dense {method} k={k}: {dt:.3f} s for {B} queries", file=sys.stderr, flush=True)
+    ctx.close()
+    return res
+
+
 def big_workload(a, lcemd):
     """The 1M-word / 1M-document workload: (1) the precision variant -- one
     symmetric ACT k=8 top-16 call over the whole query batch with float32,
@@ -466,6 +504,7 @@ def main():
     ctx.close()
     image = None if a.no_big else image_section(a, lcemd)
     selfjoin = None if a.no_big else selfjoin_section(a, lcemd)
+    dense = None if a.no_big else dense_section(a, lcemd)
     big = None if a.no_big else big_workload(a, lcemd)
 
     out = {
@@ -493,6 +532,7 @@ def main():
         "counters": counters,
         "image": image,
         "selfjoin": selfjoin,
+        "image_bg": dense,
         "text_1M": big,
     }
     print(json.dumps(out))

@@ -102,6 +102,14 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1812_02091_amd.build`")
+    # One HIP runtime per process: torch bundles a runtime with the same
+    # soname as the system one the library links, and whichever is loaded
+    # first serves both.  Load torch's first so that torch tensors and the
+    # library share it (torch fails to find the GPU under the other one).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
