@@ -38,6 +38,7 @@ int fail(lcemd_ctx* c, int code, const char* fmt, ...) {
 void free_db(lcemd_ctx* c) {
   dfree((void*&)c->xptr);
   dfree((void*&)c->xcv);
+  dfree((void*&)c->xperm);
   dfree((void*&)c->xcol);
   dfree((void*&)c->used);
   dfree((void*&)c->xmax);
@@ -397,7 +398,7 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     if ((rc = prof_begin(c, "phase2", a2))) return rc;
     unsigned long long* p2c;
     if ((rc = wsget(c, "p2_counters", 8, p2c))) return rc;
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, ZW, a.zw_nq, KT, nq, nullptr,
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->xperm, ZW, a.zw_nq, KT, nq, nullptr,
                                        out + q0 * ld, ld, p2c, c->stream));
     if ((rc = prof_end(c))) return rc;
     q0 += nq;
@@ -648,6 +649,7 @@ int lcemd_load_database(lcemd_ctx* c, const int64_t* rowptr, const int32_t* col,
   free_db(c);
   if ((rc = dalloc(c, c->xptr, n + 1, "rowptr")) || (rc = dalloc(c, c->xcv, nnz, "database entries")) ||
       (rc = dalloc(c, c->xcol, nnz, "database word ids")) || (rc = dalloc(c, c->used, used.size(), "used vocabulary")) ||
+      (rc = dalloc(c, c->xperm, n, "length order")) ||
       (rc = dalloc(c, c->xmax, used.size(), "word maxima"))) {
     free_db(c);
     return rc;
@@ -655,6 +657,13 @@ int lcemd_load_database(lcemd_ctx* c, const int64_t* rowptr, const int32_t* col,
   HIPCHK(c, hipMemcpy(c->xptr, P, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->xcv, cv.data(), sizeof(int2) * nnz, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->xcol, Cc, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+  {
+    // documents by length (phase 2 runs documents of a length side by side)
+    std::vector<int32_t> perm(n);
+    for (int64_t r = 0; r < n; ++r) perm[r] = (int32_t)r;
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return P[x + 1] - P[x] < P[y + 1] - P[y]; });
+    HIPCHK(c, hipMemcpy(c->xperm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  }
   HIPCHK(c, hipMemcpy(c->used, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->xmax, xmax.data(), sizeof(float) * used.size(), hipMemcpyHostToDevice));
   c->n = n;

@@ -166,8 +166,10 @@ hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 // Resident workgroups per CU for a kernel (cached) and the CU count.
 int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t items);
 // Phase 2 on a persistent grid: the query count is nq_dev[0] when nq_dev is
-// not null (fixed-shape batches), else nq.  counters: 8 u64, zeroed here.
-hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n, int64_t nnz,
+// not null (fixed-shape batches; nq is then its largest value), else nq.
+// perm: the documents in order of length (used for batches of up to 32
+// queries).  counters: 8 u64, zeroed here.
+hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n, const int32_t* perm,
                                     const float2* ZW, int64_t zw_nq, int KT, int64_t nq,
                                     const int* nq_dev, float* out, int64_t ld,
                                     unsigned long long* counters, hipStream_t s);

@@ -6,12 +6,18 @@
 // valid entry carries w = +inf, so the walk below is Eq. (6)-(8) followed by
 // Eq. (9) (the rest of the mass at the last distance) and always ends.
 //
-// Layout and mapping: a wave owns one database row at a time; its lanes
-// stride over the row's non-zeros (coalesced 8-byte (word, weight) loads),
-// apply a group of kQB queries' tables to each non-zero, then reduce across
-// the wave with a fixed butterfly.  The per-row sum therefore has a fixed
-// order that does not depend on which other queries or rows share the
-// launch.
+// Layout and mapping: a wave's 64 lanes are QL consecutive queries times
+// 64/QL documents.  A lane walks its document's non-zeros in order, so the
+// QL lanes of a document read one contiguous run of the table (QL entries of
+// 16 bytes per non-zero, the interleaved layout) and every (query, document)
+// sum has one fixed order: groups of eight consecutive non-zeros summed as a
+// binary tree, the groups accumulated in order with Kahan compensation (the
+// error stays a few ulps for rows of any length) -- the same bits whatever
+// QL, the batch or the launch.  QL = 64 for batches of more
+// than 32 queries (then a wave works on one document at a time); smaller
+// batches put several documents in a wave, taken in order of length (a
+// permutation made when the database is loaded) so that the lanes of a wave
+// finish together.
 #include <algorithm>
 #include <climits>
 #include <mutex>
@@ -21,22 +27,8 @@
 
 namespace lcemd {
 
-// Queries per work item (one contiguous table run per non-zero): 16 when
-// the database is large (fewer passes over X), 8 otherwise (half the
-// registers, twice the resident waves for a latency-bound gather).
-constexpr int kQBLarge = 16, kQBSmall = 8;
-constexpr int64_t kLargeX = int64_t(64) << 20;  // bytes of X records
-constexpr int kItemDocs = 16;  // database rows per work item of the persistent kernel
-
-__device__ __forceinline__ float wave_sum(float t) {
-  t += __shfl_xor(t, 32);
-  t += __shfl_xor(t, 16);
-  t += __shfl_xor(t, 8);
-  t += __shfl_xor(t, 4);
-  t += __shfl_xor(t, 2);
-  t += __shfl_xor(t, 1);
-  return t;
-}
+constexpr int kUnroll = 8;       // non-zeros whose table loads are in flight together
+constexpr int kItemSlots = 16;   // document slots per lane and work item
 
 // One transfer step of Eq. (6)-(8) against table entry (z, w).
 __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
@@ -45,96 +37,94 @@ __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
   acc = fmaf(r, z, acc);
 }
 
-// Costs of database row u against queries q0 .. q0+nqb-1 (one wave).  For
-// a non-zero of word r, the first pair of table entries of the kQB queries
-// is one contiguous run (see zw_at); the kQB 16-byte loads are all issued
-// before any is consumed (the walk along a row is a chain of dependent
-// loads otherwise).  Entries past a row's sink are never used: the sink
-// leaves no mass.
-template <int kQB>
-__device__ __forceinline__ void doc_costs(int lane, int64_t u, int64_t q0, int nqb,
-                                          const int64_t* __restrict__ xptr,
-                                          const int2* __restrict__ xcv,
-                                          const float4* __restrict__ ZP, int64_t zw_nq, int KP,
-                                          float* __restrict__ out, int64_t ld) {
-  const int64_t e0 = xptr[u], e1 = xptr[u + 1];
-  float t[kQB];
+// Cost of document u against query q (one lane): the non-zeros in order,
+// kUnroll at a time with their first table pairs loaded together; further
+// pairs are loaded together for every non-zero that still has mass.
+// Entries past a row's sink are never used: the sink leaves no mass.
+__device__ __forceinline__ float doc_cost(int64_t e0, int64_t e1, const int2* __restrict__ xcv,
+                                          const float4* __restrict__ Zq, int64_t zw_nq, int KP) {
+  static_assert(kUnroll == 8, "the group sum below is a tree over 8 terms");
+  float t = 0.f, comp = 0.f;
+  for (int64_t e = e0; e < e1; e += kUnroll) {
+    const int cnt = (int)min((int64_t)kUnroll, e1 - e);
+    int2 cv[kUnroll];
 #pragma unroll
-  for (int q = 0; q < kQB; ++q) t[q] = 0.f;
-  for (int64_t e = e0 + lane; e < e1; e += 64) {
-    const int2 cv = xcv[e];
-    const float x = __int_as_float(cv.y);
-    const float4* base = ZP + (int64_t)cv.x * KP * zw_nq + q0;
-    float4 f[kQB];
+    for (int k = 0; k < kUnroll; ++k) cv[k] = k < cnt ? xcv[e + k] : make_int2(0, 0);
+    const float4* base[kUnroll];
+    float4 f[kUnroll];
 #pragma unroll
-    for (int q = 0; q < kQB; ++q) f[q] = base[min(q, nqb - 1)];
-    // walk all queries one pair of entries at a time, so the loads of a
-    // further pair for every query that still has mass go out together
-    float rem[kQB], acc[kQB];
+    for (int k = 0; k < kUnroll; ++k) {
+      base[k] = Zq + (int64_t)cv[k].x * KP * zw_nq;
+      f[k] = k < cnt ? base[k][0] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float rem[kUnroll], acc[kUnroll];
     bool any = false;
 #pragma unroll
-    for (int q = 0; q < kQB; ++q) {
-      rem[q] = x;
-      acc[q] = 0.f;
-      step(rem[q], acc[q], f[q].x, f[q].y);
-      if (rem[q] > 0.f) step(rem[q], acc[q], f[q].z, f[q].w);
-      any = any || (q < nqb && rem[q] > 0.f);
+    for (int k = 0; k < kUnroll; ++k) {
+      rem[k] = __int_as_float(cv[k].y);  // 0 for the padding slots
+      acc[k] = 0.f;
+      step(rem[k], acc[k], f[k].x, f[k].y);
+      if (rem[k] > 0.f) step(rem[k], acc[k], f[k].z, f[k].w);
+      any = any || rem[k] > 0.f;
     }
     for (int p = 1; any && p < KP; ++p) {
 #pragma unroll
-      for (int q = 0; q < kQB; ++q)
-        if (q < nqb && rem[q] > 0.f) f[q] = base[p * zw_nq + q];
+      for (int k = 0; k < kUnroll; ++k)
+        if (rem[k] > 0.f) f[k] = base[k][p * zw_nq];
       any = false;
 #pragma unroll
-      for (int q = 0; q < kQB; ++q) {
-        if (q < nqb && rem[q] > 0.f) {
-          step(rem[q], acc[q], f[q].x, f[q].y);
-          if (rem[q] > 0.f) step(rem[q], acc[q], f[q].z, f[q].w);
-          any = any || rem[q] > 0.f;
+      for (int k = 0; k < kUnroll; ++k) {
+        if (rem[k] > 0.f) {
+          step(rem[k], acc[k], f[k].x, f[k].y);
+          if (rem[k] > 0.f) step(rem[k], acc[k], f[k].z, f[k].w);
+          any = any || rem[k] > 0.f;
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < kQB; ++q)
-      if (q < nqb) t[q] += acc[q];
+    // padding slots hold exact zeros
+    const float g = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    const float y = g - comp;
+    const float tt = t + y;
+    comp = (tt - t) - y;
+    t = tt;
   }
-#pragma unroll
-  for (int q = 0; q < kQB; ++q) {
-    const float s = wave_sum(t[q]);
-    if (lane == 0 && q < nqb) out[(q0 + q) * ld + u] = s;
-  }
+  return t;
 }
 
-// Persistent variant: a grid of resident workgroups whose waves pull
-// (query group, kItemDocs database rows) items from eight work counters, one per
-// XCD, each counter walking a contiguous eighth of the items (so an XCD
-// keeps a few queries' tables hot in its L2).  For fixed-shape batches the
+// Persistent grid: waves pull (query group of QL, 64/QL x kItemSlots
+// documents) items from eight work counters, one per XCD, each walking a
+// contiguous eighth of the items, query group major (an XCD keeps one
+// group's slice of the tables hot in its L2).  For fixed-shape batches the
 // live query count is read from device memory.  Every wave exits once its
 // counter passes the end of its range.
-template <int kQB>
-__global__ __launch_bounds__(kThreads, kQB == kQBSmall ? 4 : 1) void k_phase2_persistent(
+template <int QL>
+__global__ __launch_bounds__(kThreads) void k_phase2_persistent(
     const int64_t* __restrict__ xptr, const int2* __restrict__ xcv, int64_t n,
-    const float4* __restrict__ ZP, int64_t zw_nq, int KP, int64_t nq_arg,
-    const int* __restrict__ nq_dev, float* __restrict__ out, int64_t ld,
+    const int32_t* __restrict__ perm, const float4* __restrict__ ZP, int64_t zw_nq, int KP,
+    int64_t nq_arg, const int* __restrict__ nq_dev, float* __restrict__ out, int64_t ld,
     unsigned long long* __restrict__ counters) {
-  const int lane = threadIdx.x & 63;
+  constexpr int S = 64 / QL;  // documents side by side
+  constexpr int64_t kDocs = (int64_t)S * kItemSlots;
+  const int lane = threadIdx.x & 63, qs = lane % QL, ds = lane / QL;
   const int xcd = blockIdx.x & 7;
   const int64_t nq = nq_dev ? (int64_t)*nq_dev : nq_arg;
-  const int64_t nd = (n + kItemDocs - 1) / kItemDocs;
-  const int64_t total = (nq + kQB - 1) / kQB * nd;
+  const int64_t nd = (n + kDocs - 1) / kDocs;
+  const int64_t total = (nq + QL - 1) / QL * nd;
   const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
   while (true) {
     unsigned long long it = 0;
     if (lane == 0) it = atomicAdd(&counters[xcd], 1ull);
     const int64_t item = lo + (int64_t)__shfl((long long)it, 0);
     if (item >= hi) break;
-    const int64_t q0 = (item / nd) * kQB;
-    const int nqb = (int)min((int64_t)kQB, nq - q0);
-    const int64_t ubase = (item % nd) * kItemDocs;
-    for (int j = 0; j < kItemDocs; ++j) {
-      const int64_t u = ubase + j;
-      if (u >= n) break;
-      doc_costs<kQB>(lane, u, q0, nqb, xptr, xcv, ZP, zw_nq, KP, out, ld);
+    const int64_t q = (item / nd) * QL + qs;
+    if (q >= nq) continue;
+    const float4* Zq = ZP + q;
+    const int64_t d0 = (item % nd) * kDocs + ds;
+    for (int j = 0; j < kItemSlots; ++j) {
+      const int64_t i = d0 + (int64_t)j * S;
+      if (i >= n) break;
+      const int64_t u = S > 1 ? (int64_t)perm[i] : i;
+      out[q * ld + u] = doc_cost(xptr[u], xptr[u + 1], xcv, Zq, zw_nq, KP);
     }
   }
 }
@@ -183,29 +173,32 @@ int persistent_grid(const void* fn, int threads, size_t shmem, int64_t items) {
   return (int)grid;
 }
 
-template <int kQB>
-static hipError_t launch_p2(const int64_t* xptr, const int2* xcv, int64_t n, const float2* ZW,
-                            int64_t zw_nq, int KT, int64_t nq, const int* nq_dev, float* out,
-                            int64_t ld, unsigned long long* counters, hipStream_t s) {
-  // items (one per wave) bound the grid when the batch size is known here
-  const int64_t items = nq_dev ? INT64_MAX / 2 : (nq + kQB - 1) / kQB * ((n + kItemDocs - 1) / kItemDocs) * 64;
-  const int grid = persistent_grid((const void*)k_phase2_persistent<kQB>, kThreads, 0, items);
+template <int QL>
+static hipError_t launch_p2(const int64_t* xptr, const int2* xcv, int64_t n, const int32_t* perm,
+                            const float2* ZW, int64_t zw_nq, int KT, int64_t nq, const int* nq_dev,
+                            float* out, int64_t ld, unsigned long long* counters, hipStream_t s) {
+  // waves needed at most (bounds the grid)
+  const int64_t items = (nq + QL - 1) / QL * ((n + (64 / QL) * kItemSlots - 1) / ((64 / QL) * kItemSlots));
+  const int grid = persistent_grid((const void*)k_phase2_persistent<QL>, kThreads, 0, (items + 3) / 4);
   if (grid <= 0) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(k_phase2_persistent<kQB>, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n,
+  hipLaunchKernelGGL(k_phase2_persistent<QL>, dim3(grid), dim3(kThreads), 0, s, xptr, xcv, n, perm,
                      (const float4*)ZW, zw_nq, (int)zw_pairs(KT), nq, nq_dev, out, ld, counters);
   return hipGetLastError();
 }
 
-hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n, int64_t nnz,
+hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n, const int32_t* perm,
                                     const float2* ZW, int64_t zw_nq, int KT, int64_t nq,
                                     const int* nq_dev, float* out, int64_t ld,
                                     unsigned long long* counters, hipStream_t s) {
-  if (n <= 0 || (!nq_dev && nq <= 0)) return hipSuccess;
+  // nq: the batch size, or with nq_dev the largest live count
+  if (n <= 0 || nq <= 0) return hipSuccess;
   hipError_t e = launch_zero_ints((int*)counters, 16, s);
   if (e != hipSuccess) return e;
-  if (nnz * 8 > kLargeX)
-    return launch_p2<kQBLarge>(xptr, xcv, n, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
-  return launch_p2<kQBSmall>(xptr, xcv, n, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
+  if (nq > 32) return launch_p2<64>(xptr, xcv, n, perm, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
+  if (!perm) return hipErrorInvalidValue;
+  if (nq > 16) return launch_p2<32>(xptr, xcv, n, perm, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
+  if (nq > 8) return launch_p2<16>(xptr, xcv, n, perm, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
+  return launch_p2<8>(xptr, xcv, n, perm, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
 }
 
 __global__ __launch_bounds__(kThreads) void k_max_inplace(float* a, const float* b, int64_t count) {

@@ -190,7 +190,7 @@ int issue(lcemd_server* s, Lane& L) {
     a.fix_cap = kFixCapLane;
     if ((rc = p1_launch(c, a, P1_TABLE, s->prec, s->KT, LCEMD_SERVE_MAX_HIST, LCEMD_SERVE_MAX_HIST))) break;
     HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->nnz, L.ZW, zw_pitch(s->B), s->KT, s->B, L.nq,
+    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->xperm, L.ZW, zw_pitch(s->B), s->KT, s->B, L.nq,
                                        L.d2q, c->n, L.ctr + 8, L.stream));
     HIPCHK(c, launch_select(L.d2q, c->n, c->n, s->B, s->cld, nullptr, -1, L.cand, L.seltmp, L.stream));
     P1Args p = a;
