@@ -322,6 +322,7 @@ P1Args base_args(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o) {
   a.vnorm = c->vnorm;
   a.Vb = c->Vb;
   a.m_pad = c->m_pad;
+  a.m4 = (c->m + 3) / 4;
   a.method = o->method;
   a.k = o->method == LCEMD_ACT ? o->k : 1;
   a.n = c->n;
@@ -514,6 +515,7 @@ int lcemd_create(lcemd_ctx** out, int device) {
   }
   c->stream = c->own_stream;
   if (const char* fk = getenv("LCEMD_FORCE_KERNEL")) c->force_kernel = atoi(fk);
+  if (const char* sc = getenv("LCEMD_SYM_CANDIDATES")) c->sym_candidates = atoi(sc);
   *out = c;
   return LCEMD_OK;
 }
@@ -789,7 +791,11 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
     // exact symmetric top-l by lower-bound pruning (SYM >= D2Q)
     std::vector<int32_t> rows(B);
     for (int64_t b = 0; b < B; ++b) rows[b] = (int32_t)b;
-    int64_t Lp = std::max<int64_t>(4 * (int64_t)l, 64);
+    // first round: l + max(8, l/2) candidates (enough for every query of the
+    // text and image workloads); queries whose certificate fails go again
+    // with four times as many
+    int64_t Lp = c->sym_candidates > 0 ? std::max<int64_t>(c->sym_candidates, l)
+                                       : (int64_t)l + std::max<int64_t>(8, l / 2);
     int32_t* drows;
     int* dflags;
     if ((rc = wsget(c, "sym_rows", (size_t)B, drows)) || (rc = wsget(c, "sym_flags", (size_t)B, dflags))) return rc;

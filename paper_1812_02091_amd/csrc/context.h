@@ -50,6 +50,7 @@ struct lcemd_ctx {
   std::map<std::string, DevBuf> ws;
   size_t table_budget = size_t(12) << 30;
   int force_kernel = 0;   // test hook (LCEMD_FORCE_KERNEL): 1 = skip the 128-row kernel, 2 = deep kernel
+  int sym_candidates = 0; // test hook (LCEMD_SYM_CANDIDATES): first candidate count of the SYM top-l
   int64_t fallbacks = 0;  // tiles redone with float32 keys / deeper lists
   int64_t fixed_rows = 0; // bf16 table rows redone exactly one by one
   // profiling

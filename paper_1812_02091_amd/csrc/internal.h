@@ -51,6 +51,7 @@ struct P1Args {
   const float* vscale;    // [v] fp8 row scales
   int m8;                 // bytes per fp8 row: m_pad rounded up to 128
   int m_pad;
+  int m4;                 // float4 groups holding the m real dims, ceil(m / 4) (the rest are zero)
   // measure
   int method;             // LCEMD_RWMD / OMR / ACT / ICT
   int k;                  // ACT k

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
     float d2 = 0.f;
     if (!done) {
       const float* crow = a.V + (size_t)sm.cid[pos] * m_pad;
-      for (int d = sub * 4; d < m_pad; d += 16) {
+      for (int d = sub * 4; d < 4 * a.m4; d += 16) {  // past 4*m4 only zero padding
         const float4 x = *(const float4*)(vrow + d);
         const float4 y = *(const float4*)(crow + d);
         const float e0 = x.x - y.x, e1 = x.y - y.y, e2 = x.z - y.z, e3 = x.w - y.w;

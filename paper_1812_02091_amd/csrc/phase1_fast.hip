@@ -77,11 +77,13 @@ struct FastSmem {
   float rcost[kRows];
 };
 
-__device__ __forceinline__ float exact_d2(const float* __restrict__ V, int m_pad, int a, int b) {
+// Squared distance by direct differences; the float4 groups past the m4
+// that hold the real dims are zero padding and would add exact zeros.
+__device__ __forceinline__ float exact_d2(const float* __restrict__ V, int m_pad, int m4, int a, int b) {
   const float4* x = (const float4*)(V + (size_t)a * m_pad);
   const float4* y = (const float4*)(V + (size_t)b * m_pad);
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  const int n4 = m_pad >> 2;
+  const int n4 = (m4 + 1) & ~1;  // pairs of groups; m_pad / 4 is even
   for (int d = 0; d < n4; d += 2) {
     const float4 p = x[d], q = y[d], p2 = x[d + 1], q2 = y[d + 1];
     const float e0 = p.x - q.x, e1 = p.y - q.y, e2 = p.z - q.z, e3 = p.w - q.w;
@@ -338,7 +340,7 @@ __device__ __forceinline__ void fast_task(const P1Args& a, unsigned char* smem_r
     float d2 = sm.rvn[row] + f_unpack(e);
     bool need = PREC != PREC_F32 || !(d2 >= kGuard * (sm.rvn[row] + sm.qn[pos]));
     if (MODE != P1_TABLE_FULL && a.method == LCEMD_OMR && l == 0) need = true;
-    if (need) d2 = exact_d2(a.V, a.m_pad, sm.rid[row], sm.cid[pos]);
+    if (need) d2 = exact_d2(a.V, a.m_pad, a.m4, sm.rid[row], sm.cid[pos]);
     sm.u.zb[row * KL + l] = d2;
   }
   __syncthreads();

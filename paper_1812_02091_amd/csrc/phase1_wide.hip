@@ -28,6 +28,8 @@
 // accumulated in float32 over the original vectors (staged through LDS a
 // chunk of dims at a time), or by direct differences where cancellation
 // could bite, as for float32 keys -- and are re-sorted and cut again.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lcemd {
@@ -108,11 +110,13 @@ struct KeyOps<false, PB> {
   __device__ static T shfl1(T v) { return w_shfl1(v); }
 };
 
-__device__ __forceinline__ float w_exact_d2(const float* __restrict__ V, int m_pad, int a, int b) {
+// Squared distance by direct differences over the m4 float4 groups that
+// hold the real dims (the zero padding would add exact zeros).
+__device__ __forceinline__ float w_exact_d2(const float* __restrict__ V, int m_pad, int m4, int a, int b) {
   const float4* x = (const float4*)(V + (size_t)a * m_pad);
   const float4* y = (const float4*)(V + (size_t)b * m_pad);
   float s = 0.f;
-  const int n4 = m_pad >> 2;
+  const int n4 = m4;
   for (int d = 0; d < n4; ++d) {
     const float4 p = x[d], q = y[d];
     const float e0 = p.x - q.x, e1 = p.y - q.y, e2 = p.z - q.z, e3 = p.w - q.w;
@@ -573,7 +577,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       float d2 = sm.rvn[row] + (EX ? sm.lkx[EX ? par : 0][EX ? row * KLS + l : 0] : KeyOps<QK, PB>::key(e));
       bool need = !(d2 >= kGuardW * (sm.rvn[row] + sm.qn[pos]));
       if (MODE != P1_TABLE_FULL && a.method == LCEMD_OMR && l == 0) need = true;
-      if (need) d2 = w_exact_d2(a.V, a.m_pad, sm.rid[row], sm.cid[pos]);
+      if (need) d2 = w_exact_d2(a.V, a.m_pad, a.m4, sm.rid[row], sm.cid[pos]);
       sm.u.zb[row * KLS + l] = d2;
     }
   } else {
@@ -604,7 +608,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       if (row_ok && sub + 2 * e < len) {
         const float qn = sm.qn[ps[e]];
         float d2 = (sm.rvn[row] + qn) - 2.f * ex[e];
-        if (!(d2 >= kGuardW * (sm.rvn[row] + qn))) d2 = w_exact_d2(a.V, a.m_pad, sm.rid[row], sm.cid[ps[e]]);
+        if (!(d2 >= kGuardW * (sm.rvn[row] + qn))) d2 = w_exact_d2(a.V, a.m_pad, a.m4, sm.rid[row], sm.cid[ps[e]]);
         ex[e] = d2;
       }
     }
@@ -799,113 +803,120 @@ static hipError_t launch_wide_prec(const P1Args& a, int mode, int KL, hipStream_
   return hipErrorInvalidValue;
 }
 
-// Exact redo of single table rows (bf16 rows whose certificate failed):
-// float32 squared distances to all of the query's words by direct
-// differences, a full bitonic sort by (distance, position), then the same
-// cut and outputs as the table modes.
+// Exact redo of single table rows (rows whose selection certificate
+// failed): one wave per row computes float32 squared distances to all of the
+// query's words by direct differences (16 columns per lane in registers),
+// then takes them in ascending (distance, position) order by repeated wave
+// minimum -- at most KT + 1 of them -- with the same cut and outputs as the
+// table modes.
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* __restrict__ list) {
+  constexpr int kCols = kSegLong / 64;  // columns per lane
+  constexpr int kTake = 64;             // entries a row can take; deeper rows are flagged as overflow
+  __shared__ uint64_t taken[kThreads / 64][kTake];
   const int count = min(*a.fix_count, a.fix_cap);
-  for (int item = blockIdx.x; item < count; item += gridDim.x) {
-  __shared__ float vrow[4096];
-  __shared__ uint64_t keys[kSegLong];
-  const int tid = threadIdx.x;
-  const int64_t flat = list[item];
-  const int64_t qi = flat / a.v_used, r = flat % a.v_used;
-  const int64_t b = a.q0 + qi;
-  const int64_t s0 = a.qptr[b];
-  const int h = (int)(a.qptr[b + 1] - s0);
-  const int vid = a.used[r];
-  for (int d = tid; d < a.m_pad; d += kThreads) vrow[d] = a.V[(size_t)vid * a.m_pad + d];
-  __syncthreads();
-  for (int c = tid; c < kSegLong; c += kThreads) {
-    uint64_t kk = ~0ull;
-    if (c < h) {
-      const float4* q = (const float4*)(a.V + (size_t)a.qcol[s0 + c] * a.m_pad);
-      float d2 = 0.f;
-      for (int d = 0; d < (a.m_pad >> 2); ++d) {
-        const float4 y = q[d];
-        float e;
-        e = vrow[4 * d] - y.x; d2 = fmaf(e, e, d2);
-        e = vrow[4 * d + 1] - y.y; d2 = fmaf(e, e, d2);
-        e = vrow[4 * d + 2] - y.z; d2 = fmaf(e, e, d2);
-        e = vrow[4 * d + 3] - y.w; d2 = fmaf(e, e, d2);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = gridDim.x * (kThreads / 64);
+  uint64_t* tk = taken[wv];
+  for (int item = blockIdx.x * (kThreads / 64) + wv; item < count; item += nw) {
+    const int64_t flat = list[item];
+    const int64_t qi = flat / a.v_used, r = flat % a.v_used;
+    const int64_t b = a.q0 + qi;
+    const int64_t s0 = a.qptr[b];
+    const int h = (int)(a.qptr[b + 1] - s0);
+    const float* vrow = a.V + (size_t)a.used[r] * a.m_pad;
+    uint64_t key[kCols];
+#pragma unroll
+    for (int j = 0; j < kCols; ++j) {
+      const int c = lane + 64 * j;
+      key[j] = ~0ull;
+      if (c < h) {
+        const float4* q = (const float4*)(a.V + (size_t)a.qcol[s0 + c] * a.m_pad);
+        float d2 = 0.f;
+        for (int d = 0; d < a.m4; ++d) {  // the zero padding adds exact zeros
+          const float4 y = q[d];
+          const float4 x = *(const float4*)(vrow + 4 * d);
+          float e;
+          e = x.x - y.x; d2 = fmaf(e, e, d2);
+          e = x.y - y.y; d2 = fmaf(e, e, d2);
+          e = x.z - y.z; d2 = fmaf(e, e, d2);
+          e = x.w - y.w; d2 = fmaf(e, e, d2);
+        }
+        key[j] = w_pack(d2, (uint32_t)c);
       }
-      kk = w_pack(d2, (uint32_t)c);
     }
-    keys[c] = kk;
-  }
-  __syncthreads();
-  for (int k = 2; k <= kSegLong; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < kSegLong / 2; i += kThreads) {
-        const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-        const int hi = lo + j;
-        const bool asc = (lo & k) == 0;
-        const uint64_t x = keys[lo], y = keys[hi];
-        if ((x > y) == asc) {
-          keys[lo] = y;
-          keys[hi] = x;
+    int kef;
+    const float bound = MODE == P1_TABLE ? a.xmax[r] : INFINITY;
+    if (MODE == P1_TABLE_FULL) kef = min(a.k, h);
+    else if (a.method == LCEMD_ICT) kef = h;
+    else if (a.method == LCEMD_OMR) kef = min(2, h);
+    else if (a.method == LCEMD_RWMD) kef = 1;
+    else kef = min(a.k, h);
+    const int limit = min(MODE == P1_TABLE ? min(h, a.KT + 1) : min(h, a.k), kTake);
+    int D = 0;
+    float Pc = 0.f;
+    bool done = false;  // a cut was reached
+    for (int l = 0; l < limit; ++l) {
+      uint64_t m = ~0ull;
+#pragma unroll
+      for (int j = 0; j < kCols; ++j) m = key[j] < m ? key[j] : m;
+#pragma unroll
+      for (int sh = 32; sh >= 1; sh >>= 1) {
+        int lo = (int)(uint32_t)m, hi = (int)(uint32_t)(m >> 32);
+        lo = __shfl_xor(lo, sh);
+        hi = __shfl_xor(hi, sh);
+        const uint64_t o = ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+        m = o < m ? o : m;
+      }
+#pragma unroll
+      for (int j = 0; j < kCols; ++j)
+        if (key[j] == m) key[j] = ~0ull;  // keys are distinct (position bits)
+      if (lane == 0) tk[l] = m;
+      ++D;
+      Pc += a.qval[s0 + (uint32_t)m];
+      done = D >= kef || D == h;
+      if (MODE == P1_TABLE)
+        done = done || Pc >= bound || (a.method == LCEMD_OMR && l == 0 && w_unpack(m) != 0.f);
+      if (done) break;
+    }
+    if (lane == 0) {  // the lane that recorded the taken entries
+      if (MODE == P1_TABLE) {
+        if (D > a.KT || !done) {  // deeper than the table, or than kTake entries
+          a.overflow[0] = 1;
+        } else {
+          zw_write_row(a.ZW, a.zw_nq, a.KT, qi, r, D,
+                       [&](int l) { return sqrtf(fmaxf(w_unpack(tk[l]), 0.f)); },
+                       [&](int l) { return l == D - 1 ? INFINITY : a.qval[s0 + (uint32_t)tk[l]]; });
+        }
+      } else {
+        const int64_t o0 = flat * (int64_t)a.k;
+        for (int l = 0; l < a.k; ++l) {
+          if (l < D) {
+            const int pos = (int)(uint32_t)tk[l];
+            a.S[o0 + l] = pos;
+            a.Z[o0 + l] = sqrtf(fmaxf(w_unpack(tk[l]), 0.f));
+            a.W[o0 + l] = a.qval[s0 + pos];
+          } else {
+            a.S[o0 + l] = -1;
+            a.Z[o0 + l] = 0.f;
+            a.W[o0 + l] = 0.f;
+          }
         }
       }
-      __syncthreads();
     }
-  }
-  if (tid == 0) {
-  int kef;
-  const float bound = MODE == P1_TABLE ? a.xmax[r] : INFINITY;
-  if (MODE == P1_TABLE_FULL) kef = min(a.k, h);
-  else if (a.method == LCEMD_ICT) kef = h;
-  else if (a.method == LCEMD_OMR) kef = min(2, h);
-  else if (a.method == LCEMD_RWMD) kef = 1;
-  else kef = min(a.k, h);
-  int D = 0;
-  float Pc = 0.f;
-  for (int l = 0; l < h; ++l) {
-    ++D;
-    Pc += a.qval[s0 + (uint32_t)keys[l]];
-    if (D >= kef) break;
-    if (MODE == P1_TABLE) {
-      if (Pc >= bound) break;
-      if (a.method == LCEMD_OMR && l == 0 && w_unpack(keys[0]) != 0.f) break;
-    }
-  }
-  if (MODE == P1_TABLE) {
-    if (D > a.KT) {
-      a.overflow[0] = 1;
-    } else {
-      zw_write_row(a.ZW, a.zw_nq, a.KT, qi, r, D,
-                   [&](int l) { return sqrtf(fmaxf(w_unpack(keys[l]), 0.f)); },
-                   [&](int l) { return l == D - 1 ? INFINITY : a.qval[s0 + (uint32_t)keys[l]]; });
-    }
-  } else {
-    const int64_t o0 = flat * (int64_t)a.k;
-    for (int l = 0; l < a.k; ++l) {
-      if (l < D) {
-        const int pos = (int)(uint32_t)keys[l];
-        a.S[o0 + l] = pos;
-        a.Z[o0 + l] = sqrtf(fmaxf(w_unpack(keys[l]), 0.f));
-        a.W[o0 + l] = a.qval[s0 + pos];
-      } else {
-        a.S[o0 + l] = -1;
-        a.Z[o0 + l] = 0.f;
-        a.W[o0 + l] = 0.f;
-      }
-    }
-  }
-  }
-  __syncthreads();
   }
 }
 
 hipError_t launch_fix_rows(const P1Args& a, int mode, int count, hipStream_t s) {
   // `count` bounds the grid; the kernel reads the live count from a.fix_count
   if (count <= 0) return hipSuccess;
-  if (a.m_pad > 4096) return hipErrorInvalidValue;
+  if (mode == P1_TABLE_FULL && a.k > 64) return hipErrorInvalidValue;
+  const int per = kThreads / 64;
+  const unsigned grid = (unsigned)std::min<int64_t>((count + per - 1) / per, 65536);
   if (mode == P1_TABLE)
-    hipLaunchKernelGGL(k_fix_rows<P1_TABLE>, dim3((unsigned)count), dim3(kThreads), 0, s, a, a.fix_list);
+    hipLaunchKernelGGL(k_fix_rows<P1_TABLE>, dim3(grid), dim3(kThreads), 0, s, a, a.fix_list);
   else if (mode == P1_TABLE_FULL)
-    hipLaunchKernelGGL(k_fix_rows<P1_TABLE_FULL>, dim3((unsigned)count), dim3(kThreads), 0, s, a, a.fix_list);
+    hipLaunchKernelGGL(k_fix_rows<P1_TABLE_FULL>, dim3(grid), dim3(kThreads), 0, s, a, a.fix_list);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -166,6 +166,7 @@ int issue(lcemd_server* s, Lane& L) {
     a.V = c->V;
     a.vnorm = c->vnorm;
     a.m_pad = c->m_pad;
+    a.m4 = (c->m + 3) / 4;
     a.method = s->cfg.method;
     a.k = s->cfg.method == LCEMD_ACT ? s->cfg.k : 1;
     a.n = c->n;
@@ -434,7 +435,9 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   s->l = cfg->l;
   s->KT = method_depth(cfg->method, cfg->k, LCEMD_SERVE_MAX_HIST);
   s->depth_pair = method_depth(cfg->method, cfg->k, c->db_hmax);
-  s->use = (int)std::min<int64_t>(std::max(4 * cfg->l, 64), c->n);
+  // candidates per query (twice the text workload's need at l = 16): a query
+  // whose certificate fails is finished by lcemd_topl
+  s->use = (int)std::min<int64_t>(std::max(2 * cfg->l, cfg->l + 16), c->n);
   s->cld = s->use < c->n ? s->use + 1 : s->use;
   if (s->cld > kSelectBuf / 2) s->use = kSelectBuf / 2 - 1, s->cld = s->use + 1;
   // admission by device memory: lanes x slots x per-query state <= budget
