@@ -65,7 +65,7 @@ def phase1_kernel(method, k, precision):
         kl *= 2
     prec = 0 if margin == 0 else 1
     if depth + margin <= 32:
-        return f"k_phase1_wide<0, {kl}, {prec}>"
+        return f"k_phase1_wide<0, {kl}, {prec}, false>"
     return "k_phase1_fast<0, 64, 0>" if depth <= 64 else "k_phase1_f32"
 
 

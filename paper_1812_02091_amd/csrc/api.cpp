@@ -660,10 +660,14 @@ int lcemd_load_database(lcemd_ctx* c, const int64_t* rowptr, const int32_t* col,
   HIPCHK(c, hipMemcpy(c->xcv, cv.data(), sizeof(int2) * nnz, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->xcol, Cc, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
   {
-    // documents by length (phase 2 runs documents of a length side by side)
+    // documents by length within aligned windows of 128 (phase 2 runs
+    // documents of a similar length side by side; its outputs stay within a
+    // window)
     std::vector<int32_t> perm(n);
     for (int64_t r = 0; r < n; ++r) perm[r] = (int32_t)r;
-    std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return P[x + 1] - P[x] < P[y + 1] - P[y]; });
+    for (int64_t w0 = 0; w0 < n; w0 += 128)
+      std::stable_sort(perm.begin() + w0, perm.begin() + std::min<int64_t>(n, w0 + 128),
+                       [&](int32_t x, int32_t y) { return P[x + 1] - P[x] < P[y + 1] - P[y]; });
     HIPCHK(c, hipMemcpy(c->xperm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   }
   HIPCHK(c, hipMemcpy(c->used, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice));

@@ -42,7 +42,7 @@ struct lcemd_ctx {
   int64_t* xptr = nullptr;
   int2* xcv = nullptr;
   int32_t* xcol = nullptr;
-  int32_t* xperm = nullptr;  // database rows in order of length
+  int32_t* xperm = nullptr;  // database rows by length within windows of 128
   int32_t* used = nullptr;
   float* xmax = nullptr;
   std::vector<int32_t> used_host;

@@ -11,7 +11,9 @@
 //
 // Selection: after a pass the keys |c|^2 - 2 <v, c> go to LDS 64 columns at
 // a time and two lanes per row merge them into the row's sorted candidate
-// list (packed (key, position); position breaks ties), cut at k_eff = min(k,
+// list (packed (key, position); position breaks ties; for lists of 8 or more
+// entries each lane first sorts its 32 keys in registers and the merge takes
+// from their heads, else it scans them for the next), cut at k_eff = min(k,
 // h) (Alg. 3; 1 for RWMD, 2 for OMR) or as soon as the listed capacities
 // reach the row's bound (Lemma 1/2: no transfer of at most that much mass
 // passes this point).
@@ -502,6 +504,29 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
         kk[2 * j2] = KO::pack(kv.x, (uint32_t)c) | m0;
         kk[2 * j2 + 1] = KO::pack(kv.y, (uint32_t)(c + 1)) | m1;
       }
+      // lists of 8 or more entries: the thread's 32 keys are sorted once
+      // (bitonic network in registers) and the merge takes from their head;
+      // shorter lists scan the keys for the next one instead
+      constexpr bool kSorted = QK && KL >= 8;
+      if constexpr (kSorted) {
+#pragma unroll
+        for (int kb = 2; kb <= 32; kb <<= 1) {
+#pragma unroll
+          for (int jb = kb >> 1; jb > 0; jb >>= 1) {
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+              const int l2 = i ^ jb;
+              if (l2 > i) {
+                const KT_ x = kk[i], y = kk[l2];
+                const KT_ lo = x < y ? x : y, hi = x < y ? y : x;
+                const bool up = (i & kb) == 0;
+                kk[i] = up ? lo : hi;
+                kk[l2] = up ? hi : lo;
+              }
+            }
+          }
+        }
+      }
       const KT_* cur = &sm.lst[par][row * KLS];
       KT_* nxt = &sm.lst[par ^ 1][row * KLS];
       const float* curx = &sm.lkx[EX ? par : 0][EX ? row * KLS : 0];
@@ -519,12 +544,17 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
       while (__any(act)) {
         KT_ best = KO::kNone;
         if (act) {
+          if constexpr (kSorted) {
+            best = kk[0];
+          } else {
 #pragma unroll
-          for (int j = 0; j < 32; ++j) {
-            const KT_ cand = kk[j] > last ? kk[j] : KO::kNone;
-            best = cand < best ? cand : best;
+            for (int j = 0; j < 32; ++j) {
+              const KT_ cand = kk[j] > last ? kk[j] : KO::kNone;
+              best = cand < best ? cand : best;
+            }
           }
         }
+        const KT_ mine = best;
         const KT_ o = KO::shfl1(best);
         best = o < best ? o : best;
         if (act) {
@@ -543,8 +573,18 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
             if constexpr (EX) {
               if (sub == 0) nxtx[w] = lc < best ? curx[ptr] : sm.u.ck[row * kCK + (int)(KO::pos(take)) - cb];
             }
-            if (lc < best) ++ptr;
-            else last = best;
+            if (lc < best) {
+              ++ptr;
+            } else {
+              last = best;
+              if constexpr (kSorted) {
+                if (mine == best) {  // this thread's head was taken
+#pragma unroll
+                  for (int j = 0; j < 31; ++j) kk[j] = kk[j + 1];
+                  kk[31] = KO::kNone;
+                }
+              }
+            }
             if (sub == 0) nxt[w] = take;
             ++w;
             if (!cut) {

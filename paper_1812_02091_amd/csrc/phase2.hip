@@ -15,9 +15,9 @@
 // error stays a few ulps for rows of any length) -- the same bits whatever
 // QL, the batch or the launch.  QL = 64 for batches of more
 // than 32 queries (then a wave works on one document at a time); smaller
-// batches put several documents in a wave, taken in order of length (a
-// permutation made when the database is loaded) so that the lanes of a wave
-// finish together.
+// batches put several documents in a wave, taken in order of length within
+// windows of 128 documents (a permutation made when the database is loaded)
+// so that the lanes of a wave finish together while its outputs stay close.
 #include <algorithm>
 #include <climits>
 #include <mutex>
