@@ -96,15 +96,6 @@ def test_dense_selfjoin(L, small):
         P.check_topl(idx[b], dist[b], row, 4, f"row {b}")
 
 
-def _excess(db, qv, u_list, d2q):
-    q = qv.astype(np.float64)
-    out = []
-    for u in u_list:
-        p = db.row(int(u))[1].astype(np.float64)
-        out.append(np.maximum(p - q, 0).sum() if d2q else np.maximum(q - p, 0).sum())
-    return np.array(out)
-
-
 def test_dense_full_size_closed_forms(L):
     """60,000 dense images, 4 queries: RWMD all exactly 0; OMR and ACT(2)
     against the closed form on every one of the 240,000 pairs."""
@@ -134,3 +125,14 @@ def test_dense_full_size_closed_forms(L):
         qv = w.queries.row(b)[1].astype(np.float64)
         cf = np.maximum(np.maximum(X - qv, 0).sum(1), np.maximum(qv - X, 0).sum(1))
         P.check_topl(idx[b], dist[b], cf, 16, f"query {b}")
+
+
+def test_serving_rejects_long_database_rows(L, small):
+    """Serving is sized for histograms of at most 512 words: a database of
+    784-word rows is refused at start, with the context left usable."""
+    w, ref = small
+    ctx = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val)
+    with pytest.raises(L.LcemdError):
+        L.Server(ctx, method="act", k=2, l=4, max_slots=4)
+    q = (w.queries.rowptr, w.queries.col, w.queries.val)
+    P.assert_distances(ctx.distances(*q, method="act", k=2, direction="d2q"), ref[("act", 2, "d2q")], "after refusal")

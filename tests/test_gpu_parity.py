@@ -365,3 +365,35 @@ def test_topl_fp8_text_agreement(text_small):
     agree = np.mean([len(set(i32[b]) & set(i8[b])) / 16 for b in range(w.queries.n)])
     assert agree >= 0.95, agree
     assert np.all(np.diff(d8, axis=1) >= 0)
+
+
+def test_device_results_ordered_on_torch_stream(tiny):
+    """Device-pointer calls run on torch's current stream (its default stream
+    has the null handle): a copy to the host right after the call, with no
+    explicit synchronisation, sees the finished results."""
+    import torch
+
+    w, ctx, _ = tiny
+    dev = torch.device("cuda:0")
+    q = [torch.from_numpy(x).to(dev) for x in _q(w)]
+    gh = ctx.distances(*_q(w), method="act", k=2, direction="d2q")
+    for _ in range(3):
+        gd = ctx.distances(*q, method="act", k=2, direction="d2q")
+        assert np.array_equal(gd.cpu().numpy(), gh)
+
+
+@pytest.mark.parametrize("wl", ["text", "image"])
+def test_phase2_lane_layouts_agree_bitwise(L, wl):
+    """Phase 2 puts 64 queries of one document in a wave for batches of more
+    than 32, and 32/16/8 queries of several documents (taken by length)
+    below; the per-pair sums have one fixed order, so every batch size gives
+    the same bits."""
+    w = make_workload(wl, n=300, B=40) if wl == "image" else make_workload(wl, n=300, B=40, v=4000)
+    say(f"[gpu] phase-2 lane layouts, {wl}")
+    ctx = _ctx(L, w)
+    big = w.queries
+    full = ctx.distances(big.rowptr, big.col, big.val, method="act", k=4, direction="d2q")
+    for size in (20, 12, 5, 1):
+        sub = w.queries.take(list(range(size)))
+        g = ctx.distances(sub.rowptr, sub.col, sub.val, method="act", k=4, direction="d2q")
+        assert np.array_equal(g, full[:size]), size

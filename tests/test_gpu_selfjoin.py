@@ -130,3 +130,16 @@ def test_selfjoin_rejects(L, tiny):
             ctx.selfjoin_topl(l, method="act", k=2, direction="sym", **kw)
     i, d = ctx.selfjoin_topl(299, method="rwmd", direction="d2q")  # l = n - 1: every other row
     assert all(sorted(i[b].tolist()) == [x for x in range(300) if x != b] for b in range(0, 300, 50))
+
+
+def test_selfjoin_two_histograms(L):
+    """The smallest self-join: each of two histograms has the other as its
+    only neighbour, at the oracle's symmetric distance."""
+    w = make_workload("tiny", n=2, B=1)
+    ctx = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val)
+    idx, dist = ctx.selfjoin_topl(1, method="act", k=2, direction="sym")
+    assert idx[:, 0].tolist() == [1, 0]
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    c, v = w.db.row(0)
+    o = orc.row_distances(c, v, "act", 2, "sym")[1]
+    P.assert_distances(dist[:, 0], np.array([o, o]), "two histograms")
