@@ -42,6 +42,9 @@
  *   the context's stream.
  * - Ownership: loads copy into library-owned device memory (the caller may
  *   free its arrays on return); queries and outputs stay caller-owned.
+ *   Scratch (tables, distance matrices, candidate lists) is allocated by the
+ *   context on first need, grows but never shrinks, and is freed by
+ *   lcemd_destroy: a self-join of n histograms keeps its n^2 floats.
  * - A context is not thread-safe; calls on one context must be serialised.
  */
 #ifndef LCEMD_H
