@@ -11,7 +11,7 @@ vectors, which is not available here): vocabulary 70,000 x 300 unit-norm
 Gaussian embeddings, 18,000 database histograms and 1,000 queries of 50-300
 distinct Zipf(1.0) words (log-normal lengths, mean ~120), tf weights.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 import argparse
 import json
@@ -392,7 +392,7 @@ def serve_path(a, lcemd, ctx, v, n):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "lcemd runs on one GPU (sharding over several is designed, not implemented); --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     if a.copy_calibration:
