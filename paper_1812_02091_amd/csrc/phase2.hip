@@ -37,24 +37,58 @@ __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
   acc = fmaf(r, z, acc);
 }
 
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
 // Cost of document u against query q (one lane): the non-zeros in order,
 // kUnroll at a time with their first table pairs loaded together; further
 // pairs are loaded together for every non-zero that still has mass.
 // Entries past a row's sink are never used: the sink leaves no mass.
+// UNI: every lane of the wave is on this document, so its records and the
+// table row offsets are wave-uniform (scalar loads and arithmetic).
+// Otherwise the QL lanes from `glane` on share the document: its first
+// lanes load one record each and the group reads them by lane shuffle
+// (every lane of the group runs this with the same e0, e1).
+template <bool UNI>
 __device__ __forceinline__ float doc_cost(int64_t e0, int64_t e1, const int2* __restrict__ xcv,
-                                          const float4* __restrict__ Zq, int64_t zw_nq, int KP) {
+                                          const float4* __restrict__ Zq, int64_t zw_nq, int KP,
+                                          int lane, int glane) {
   static_assert(kUnroll == 8, "the group sum below is a tree over 8 terms");
+  if constexpr (UNI) {
+    e0 = uniform64(e0);
+    e1 = uniform64(e1);
+  }
+  const int64_t rstride = (int64_t)KP * zw_nq;  // float4s from one word's run to the next
   float t = 0.f, comp = 0.f;
   for (int64_t e = e0; e < e1; e += kUnroll) {
     const int cnt = (int)min((int64_t)kUnroll, e1 - e);
     int2 cv[kUnroll];
+    if constexpr (UNI) {
+      if (cnt == kUnroll) {
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) cv[k] = k < cnt ? xcv[e + k] : make_int2(0, 0);
+        for (int k = 0; k < kUnroll; ++k) cv[k] = xcv[e + k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) cv[k] = k < cnt ? xcv[e + k] : make_int2(0, 0);
+      }
+    } else {
+      const int j = lane - glane;
+      const int2 rec = j < cnt ? xcv[e + j] : make_int2(0, 0);
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        cv[k].x = __shfl(rec.x, glane + k);
+        cv[k].y = __shfl(rec.y, glane + k);
+      }
+    }
     const float4* base[kUnroll];
     float4 f[kUnroll];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
-      base[k] = Zq + (int64_t)cv[k].x * KP * zw_nq;
+      const int w = UNI ? __builtin_amdgcn_readfirstlane(cv[k].x) : cv[k].x;
+      base[k] = Zq + (int64_t)w * rstride;
       f[k] = k < cnt ? base[k][0] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     float rem[kUnroll], acc[kUnroll];
@@ -116,15 +150,18 @@ __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
     if (lane == 0) it = atomicAdd(&counters[xcd], 1ull);
     const int64_t item = lo + (int64_t)__shfl((long long)it, 0);
     if (item >= hi) break;
+    // lanes past the batch walk the last query's table (so every lane of a
+    // document group takes part in its record shuffles) and write nothing
     const int64_t q = (item / nd) * QL + qs;
-    if (q >= nq) continue;
-    const float4* Zq = ZP + q;
+    const bool qok = q < nq;
+    const float4* Zq = ZP + (qok ? q : nq - 1);
     const int64_t d0 = (item % nd) * kDocs + ds;
     for (int j = 0; j < kItemSlots; ++j) {
       const int64_t i = d0 + (int64_t)j * S;
       if (i >= n) break;
       const int64_t u = S > 1 ? (int64_t)perm[i] : i;
-      out[q * ld + u] = doc_cost(xptr[u], xptr[u + 1], xcv, Zq, zw_nq, KP);
+      const float c = doc_cost<S == 1>(xptr[u], xptr[u + 1], xcv, Zq, zw_nq, KP, lane, ds * QL);
+      if (qok) out[q * ld + u] = c;
     }
   }
 }
