@@ -267,6 +267,7 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
   // deeper lists use float32 keys
   if (prec != LCEMD_FP32 && (depth + kMargin > 32 || c->force_kernel || mode == P1_PAIR || seg_hmax > kSegShort))
     prec = LCEMD_FP32;
+  if (a.m4 < 1 || 4 * a.m4 > a.m_pad) return fail(c, LCEMD_E_INVALID_ARG, "internal: phase-1 arguments without their dims");
   if (!a.work_ctr) {
     int rc = wsget(c, "p1_counters", 8, a.work_ctr);
     if (rc) return rc;

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
     floatx16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    for (int kc = 0; kc < m_pad; kc += kKChunk) {
+    for (int kc = 0; kc < 4 * a.m4; kc += kKChunk) {  // chunks past 4*m4 are zero padding
 #pragma unroll
       for (int it = 0; it < 2; ++it) {
         const int f = tid + it * kThreads;  // 0..511 float4 slots per tile

@@ -200,7 +200,10 @@ __device__ __forceinline__ void fast_task(const P1Args& a, unsigned char* smem_r
   // ---------------- contraction, pass by pass ----------------
   const unsigned char* base = PREC == PREC_F32 ? (const unsigned char*)a.V : (const unsigned char*)a.Vb;
   const size_t rowbytes = (size_t)a.m_pad * (PREC == PREC_F32 ? 4 : 2);
-  const int nsl = (int)(rowbytes / 128);
+  // 128-byte slices that hold real dims (the zero padding past them would
+  // add exact zeros)
+  const int realbytes = 4 * a.m4 * (PREC == PREC_F32 ? 4 : 2);
+  const int nsl = min((int)(rowbytes / 128), (realbytes + 127) / 128);
   unsigned char* stV = sm.u.st;
   unsigned char* stQ = sm.u.st + kRows * kStageStride;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;

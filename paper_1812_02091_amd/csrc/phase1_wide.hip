@@ -402,7 +402,10 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
                               : PREC == PREC_BF16 ? (const unsigned char*)a.Vb
                                                   : (const unsigned char*)a.V8;
   const size_t rowbytes = PREC == PREC_FP8 ? (size_t)a.m8 : (size_t)a.m_pad * (PREC == PREC_F32 ? 4 : 2);
-  const int nsl = (int)(rowbytes / 128);
+  // 128-byte slices that hold real dims (the zero padding past them would
+  // add exact zeros): 4 * m4 dims of 4, 2 or 1 bytes
+  const int realbytes = 4 * a.m4 * (PREC == PREC_F32 ? 4 : PREC == PREC_BF16 ? 2 : 1);
+  const int nsl = min((int)(rowbytes / 128), (realbytes + 127) / 128);
   const int li = lane & 31, lh = lane >> 5;
   const int arow = 32 * wave + li;
   const bool arow_ok = arow < nrows;
