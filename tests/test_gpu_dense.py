@@ -136,3 +136,21 @@ def test_serving_rejects_long_database_rows(L, small):
         L.Server(ctx, method="act", k=2, l=4, max_slots=4)
     q = (w.queries.rowptr, w.queries.col, w.queries.val)
     P.assert_distances(ctx.distances(*q, method="act", k=2, direction="d2q"), ref[("act", 2, "d2q")], "after refusal")
+
+
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_dense_tables_exact_ties(L, small, k):
+    """Phase-1 tables of 784-word queries (the long-segment kernel variant):
+    on the integer grid squared distances are exact in float32, so the index
+    sets equal the oracle's tie-broken sets bit for bit."""
+    w, _ = small
+    ctx = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val)
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    say(f"[gpu] dense tables k={k}")
+    S, Z, W = ctx.tables(w.queries.rowptr, w.queries.col, w.queries.val, k=k)
+    for b in range(w.queries.n):
+        qc, qw = w.queries.row(b)
+        So, Zo, Wo, R = orc.tables(qc, qw, k)
+        assert np.array_equal(S[b].astype(np.int64), So), b
+        assert np.array_equal(W[b], Wo.astype(np.float32)), b
+        assert np.allclose(Z[b], Zo, rtol=1e-6, atol=0), b
