@@ -45,6 +45,7 @@ void free_db(lcemd_ctx* c) {
   c->n = c->nnz = c->v_used = 0;
   c->db_hmax = 0;
   c->used_host.clear();
+  c->xptr_host.clear();
 }
 
 void free_emb(lcemd_ctx* c) {
@@ -316,7 +317,33 @@ int table_depth(const lcemd_opts* o, int hmax) {
   }
 }
 
-P1Args base_args(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o) {
+// The histograms whose non-zeros phase 2 walks (the "database" of Sec. 4):
+// the loaded database, or for the reverse direction the query batch.
+struct DbView {
+  int64_t n = 0, nnz = 0, v_used = 0;
+  const int64_t* xptr = nullptr;
+  const int2* xcv = nullptr;     // (compact word id, weight bits)
+  const int32_t* xcol = nullptr; // original word ids
+  const int32_t* used = nullptr; // compact id -> word id
+  const float* xmax = nullptr;   // largest weight of each used word
+  const int32_t* perm = nullptr; // rows by length within windows of 128
+};
+
+DbView db_view(lcemd_ctx* c) {
+  DbView d;
+  d.n = c->n;
+  d.nnz = c->nnz;
+  d.v_used = c->v_used;
+  d.xptr = c->xptr;
+  d.xcv = c->xcv;
+  d.xcol = c->xcol;
+  d.used = c->used;
+  d.xmax = c->xmax;
+  d.perm = c->xperm;
+  return d;
+}
+
+P1Args base_args(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o) {
   P1Args a;
   memset(&a, 0, sizeof a);
   a.V = c->V;
@@ -326,25 +353,27 @@ P1Args base_args(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o) {
   a.m4 = (c->m + 3) / 4;
   a.method = o->method;
   a.k = o->method == LCEMD_ACT ? o->k : 1;
-  a.n = c->n;
-  a.xptr = c->xptr;
-  a.xcv = c->xcv;
-  a.xcol = c->xcol;
-  a.v_used = c->v_used;
-  a.used = c->used;
-  a.xmax = c->xmax;
+  a.n = db.n;
+  a.xptr = db.xptr;
+  a.xcv = db.xcv;
+  a.xcol = db.xcol;
+  a.v_used = db.v_used;
+  a.used = db.used;
+  a.xmax = db.xmax;
   a.qptr = Q.ptr;
   a.qcol = Q.col;
   a.qval = Q.val;
   return a;
 }
 
-// D2Q distances of every query against every database row (Sec. 4):
+P1Args base_args(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o) { return base_args(c, db_view(c), Q, o); }
+
+// D2Q distances of every query against every row of `db` (Sec. 4):
 // out[b * ld + u].
-int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
+int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
   int KT = table_depth(o, Q.hmax);
   int prec = o->precision;
-  const size_t per_q = (size_t)c->v_used * sizeof(float2);
+  const size_t per_q = (size_t)db.v_used * sizeof(float2);
   int* ovf;
   int rc;
   if ((rc = wsget(c, "ovf", 1, ovf))) return rc;
@@ -354,9 +383,9 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     Bt = std::min<int64_t>(Bt, 16384);  // also bounds the rows a tile may need to redo
     const int64_t nq = std::min<int64_t>(Bt, Q.B - q0);
     float2* ZW;
-    if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * c->v_used * 2 * zw_pairs(KT), ZW))) return rc;
+    if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * db.v_used * 2 * zw_pairs(KT), ZW))) return rc;
     HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
-    P1Args a = base_args(c, Q, o);
+    P1Args a = base_args(c, db, Q, o);
     a.KT = KT;
     a.q0 = q0;
     a.nq = nq;
@@ -371,7 +400,7 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
     a.fix_count = fixc;
     a.fix_cap = kFixCap;
     int64_t H = Q.hptr[q0 + nq] - Q.hptr[q0];
-    if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)c->v_used * (double)H * (double)c->m))) return rc;
+    if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)db.v_used * (double)H * (double)c->m))) return rc;
     if ((rc = p1_launch(c, a, P1_TABLE, prec, KT, Q.hmax, Q.hmax))) return rc;
     if ((rc = prof_end(c))) return rc;
     {
@@ -396,17 +425,21 @@ int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_
         continue;
       }
     }
-    const double a2 = (double)nq * (8.0 * c->nnz + 8.0 * (c->n + 1) + 8.0 * (double)c->v_used * KT + 4.0 * c->n);
+    const double a2 = (double)nq * (8.0 * db.nnz + 8.0 * (db.n + 1) + 8.0 * (double)db.v_used * KT + 4.0 * db.n);
     if ((rc = prof_begin(c, "phase2", a2))) return rc;
     unsigned long long* p2c;
     if ((rc = wsget(c, "p2_counters", 8, p2c))) return rc;
-    HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->xperm, ZW, a.zw_nq, KT, nq, nullptr,
+    HIPCHK(c, launch_phase2_persistent(db.xptr, db.xcv, db.n, db.perm, ZW, a.zw_nq, KT, nq, nullptr,
                                        out + q0 * ld, ld, p2c, c->stream));
     if ((rc = prof_end(c))) return rc;
     q0 += nq;
     prec = o->precision;
   }
   return LCEMD_OK;
+}
+
+int run_d2q(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
+  return run_d2q(c, db_view(c), Q, o, out, ld);
 }
 
 // The L smallest keys of each row (scratch for the per-part first pass).
@@ -452,16 +485,83 @@ int run_pairs(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, P1Args a, float*
 
 // Full Q2D matrix: out[b * ld + u], in query tiles that keep the pair grid
 // within limits.
-int run_q2d_full(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
-  const int64_t per_launch = std::max<int64_t>(1, (int64_t(1) << 26) / c->n);
-  for (int64_t q0 = 0; q0 < Q.B; q0 += per_launch) {
-    const int64_t nq = std::min(per_launch, Q.B - q0);
-    P1Args a = base_args(c, Q, o);
-    a.q0 = q0;
-    a.npairs = nq * c->n;
-    int rc = run_pairs(c, Q, o, a, out + q0 * ld, ld, c->n);
-    if (rc) return rc;
+// The loaded database as a device-resident query batch (its weights copied
+// out of the (word, weight) records).
+int docs_as_queries(lcemd_ctx* c, QDev& Q) {
+  Q.B = c->n;
+  Q.nnz = c->nnz;
+  Q.ptr = c->xptr;
+  Q.col = c->xcol;
+  Q.hmax = c->db_hmax;
+  Q.device = true;
+  float* dval;
+  int rc = wsget(c, "db_val", (size_t)c->nnz, dval);
+  if (rc) return rc;
+  HIPCHK(c, launch_record_weights(c->xcv, c->nnz, dval, c->stream));
+  Q.val = dval;
+  Q.hptr = c->xptr_host;
+  return LCEMD_OK;
+}
+
+// Q2D of every query against every database row (out[b * ld + u]) by the
+// linear-complexity method with the roles swapped: the query batch is the
+// histogram set whose non-zeros phase 2 walks (its used words are the table
+// rows, its largest weight per word bounds ICT's depth, Lemma 1) and every
+// database row is a query of phase 1; Q2D(b, u) moves query b's mass into
+// row u, which is what that D2Q computes.
+int run_q2d_lc(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
+  const int64_t B = Q.B, H = Q.nnz;
+  std::vector<int32_t> col(H);
+  std::vector<float> val(H);
+  HIPCHK(c, hipMemcpyAsync(col.data(), Q.col, sizeof(int32_t) * H, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(val.data(), Q.val, sizeof(float) * H, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<int32_t> used(col);
+  std::sort(used.begin(), used.end());
+  used.erase(std::unique(used.begin(), used.end()), used.end());
+  const int64_t nu = (int64_t)used.size();
+  std::vector<int2> cv(H);
+  std::vector<float> xmax(nu, 0.f);
+  for (int64_t i = 0; i < H; ++i) {
+    const int32_t p = (int32_t)(std::lower_bound(used.begin(), used.end(), col[i]) - used.begin());
+    cv[i].x = p;
+    memcpy(&cv[i].y, &val[i], sizeof(float));
+    xmax[p] = std::max(xmax[p], val[i]);
   }
+  std::vector<int32_t> perm(B);
+  for (int64_t r = 0; r < B; ++r) perm[r] = (int32_t)r;
+  const auto& hp = Q.hptr;
+  for (int64_t w0 = 0; w0 < B; w0 += 128)
+    std::stable_sort(perm.begin() + w0, perm.begin() + std::min<int64_t>(B, w0 + 128),
+                     [&](int32_t x, int32_t y) { return hp[x + 1] - hp[x] < hp[y + 1] - hp[y]; });
+  int2* dcv;
+  int32_t *dused, *dperm;
+  float* dxmax;
+  int rc;
+  if ((rc = wsget(c, "rev_xcv", (size_t)H, dcv)) || (rc = wsget(c, "rev_used", (size_t)nu, dused)) ||
+      (rc = wsget(c, "rev_xmax", (size_t)nu, dxmax)) || (rc = wsget(c, "rev_perm", (size_t)B, dperm)))
+    return rc;
+  HIPCHK(c, hipMemcpyAsync(dcv, cv.data(), sizeof(int2) * H, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dused, used.data(), sizeof(int32_t) * nu, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dxmax, xmax.data(), sizeof(float) * nu, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, c->stream));
+  DbView d;
+  d.n = B;
+  d.nnz = H;
+  d.v_used = nu;
+  d.xptr = Q.ptr;
+  d.xcv = dcv;
+  d.xcol = Q.col;
+  d.used = dused;
+  d.xmax = dxmax;
+  d.perm = dperm;
+  QDev docs;
+  if ((rc = docs_as_queries(c, docs))) return rc;
+  float* T;
+  if ((rc = wsget(c, "rev_out", (size_t)c->n * B, T))) return rc;
+  if ((rc = run_d2q(c, d, docs, o, T, B))) return rc;  // T[u * B + b]
+  HIPCHK(c, hipStreamSynchronize(c->stream));           // host vectors above stay alive until here
+  HIPCHK(c, launch_transpose(T, c->n, B, out, ld, c->stream));
   return LCEMD_OK;
 }
 
@@ -678,6 +778,7 @@ int lcemd_load_database(lcemd_ctx* c, const int64_t* rowptr, const int32_t* col,
   c->v_used = (int64_t)used.size();
   c->db_hmax = hmax;
   c->used_host = std::move(used);
+  c->xptr_host.assign(P, P + n + 1);
   return LCEMD_OK;
 }
 
@@ -739,11 +840,11 @@ int lcemd_distances(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, flo
     if ((rc = run_d2q(c, Q, o, dout, n))) return rc;
   }
   if (o->direction == LCEMD_Q2D) {
-    if ((rc = run_q2d_full(c, Q, o, dout, n))) return rc;
+    if ((rc = run_q2d_lc(c, Q, o, dout, n))) return rc;
   } else if (o->direction == LCEMD_SYM) {
     float* tmp;
     if ((rc = wsget(c, "q2d_full", (size_t)Q.B * n, tmp))) return rc;
-    if ((rc = run_q2d_full(c, Q, o, tmp, n))) return rc;
+    if ((rc = run_q2d_lc(c, Q, o, tmp, n))) return rc;
     HIPCHK(c, launch_max_inplace(dout, tmp, Q.B * n, c->stream));
   }
   if (!Q.device) {
@@ -781,7 +882,7 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
   float* d2q;
   if ((rc = wsget(c, "d2q_full", (size_t)B * n, d2q))) return rc;
   if (o->direction == LCEMD_Q2D) {
-    if ((rc = run_q2d_full(c, Q, o, d2q, n))) return rc;
+    if ((rc = run_q2d_lc(c, Q, o, d2q, n))) return rc;
   } else {
     if ((rc = run_d2q(c, Q, o, d2q, n))) return rc;
   }
@@ -951,19 +1052,7 @@ int lcemd_selfjoin_topl(lcemd_ctx* c, const lcemd_opts* o, int32_t l, uint32_t f
   if ((rc = ensure_precision(c, o->precision))) return rc;
   // the database as a device-resident query batch
   QDev Q;
-  Q.B = n;
-  Q.nnz = c->nnz;
-  Q.ptr = c->xptr;
-  Q.col = c->xcol;
-  Q.hmax = c->db_hmax;
-  Q.device = true;
-  float* dval;
-  if ((rc = wsget(c, "db_val", (size_t)c->nnz, dval))) return rc;
-  HIPCHK(c, launch_record_weights(c->xcv, c->nnz, dval, c->stream));
-  Q.val = dval;
-  Q.hptr.resize(n + 1);
-  HIPCHK(c, hipMemcpyAsync(Q.hptr.data(), c->xptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if ((rc = docs_as_queries(c, Q))) return rc;
   float* D;
   if ((rc = wsget(c, "selfjoin", (size_t)n * n, D))) return rc;
   lcemd_opts od = *o;

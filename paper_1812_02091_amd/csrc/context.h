@@ -46,6 +46,7 @@ struct lcemd_ctx {
   int32_t* used = nullptr;
   float* xmax = nullptr;
   std::vector<int32_t> used_host;
+  std::vector<int64_t> xptr_host;  // database row pointers (host copy)
   // scratch, grow-only
   std::map<std::string, DevBuf> ws;
   size_t table_budget = size_t(12) << 30;

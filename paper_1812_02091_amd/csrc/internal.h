@@ -163,6 +163,9 @@ hipError_t launch_max_inplace(float* a, const float* b, int64_t count, hipStream
 hipError_t launch_record_weights(const int2* xcv, int64_t nnz, float* val, hipStream_t s);
 // in-place n x n: mode 0 transpose, 1 symmetric maximum
 hipError_t launch_square_pair(float* D, int64_t n, int mode, hipStream_t s);
+// out[c * ld_out + r] = in[r * cols + c] for a rows x cols row-major `in`
+hipError_t launch_transpose(const float* in, int64_t rows, int64_t cols, float* out, int64_t ld_out,
+                            hipStream_t s);
 hipError_t launch_zero_ints(int* p, int count, hipStream_t s);
 // Resident workgroups per CU for a kernel (cached) and the CU count.
 int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t items);

@@ -12,6 +12,8 @@
 // are exact as soon as the (L+1)-th candidate's D2Q key exceeds the l-th
 // best SYM key, since every other row's SYM key is at least its D2Q key.
 // Rows for which that certificate fails are flagged for a wider pass.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lcemd {
@@ -270,6 +272,38 @@ __global__ __launch_bounds__(kThreads) void k_square_pair(float* __restrict__ D,
     if (i < n && j < n) D[i * n + j] = v1;
     if (I != J && i2 < n && j2 < n) D[i2 * n + j2] = v2;
   }
+}
+
+// Rectangular transpose through 64x64 LDS tiles (coalesced reads and
+// writes): out[c * ld_out + r] = in[r * cols + c].
+__global__ __launch_bounds__(kThreads) void k_transpose(const float* __restrict__ in, int64_t rows,
+                                                        int64_t cols, float* __restrict__ out,
+                                                        int64_t ld_out) {
+  __shared__ float t[kTT][kTT + 1];
+  const int64_t c0 = (int64_t)blockIdx.x * kTT;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  // row tiles strided over the grid's y extent (which is capped)
+  for (int64_t r0 = (int64_t)blockIdx.y * kTT; r0 < rows; r0 += (int64_t)gridDim.y * kTT) {
+    for (int i = ty; i < kTT; i += kThreads / 64) {
+      const int64_t r = r0 + i, c = c0 + tx;
+      if (r < rows && c < cols) t[i][tx] = in[r * cols + c];
+    }
+    __syncthreads();
+    for (int i = ty; i < kTT; i += kThreads / 64) {
+      const int64_t c = c0 + i, r = r0 + tx;
+      if (r < rows && c < cols) out[c * ld_out + r] = t[tx][i];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_transpose(const float* in, int64_t rows, int64_t cols, float* out, int64_t ld_out,
+                            hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int64_t gx = (cols + kTT - 1) / kTT, gy = std::min<int64_t>((rows + kTT - 1) / kTT, 32768);
+  if (gx > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)gx, (unsigned)gy), dim3(kThreads), 0, s, in, rows, cols, out, ld_out);
+  return hipGetLastError();
 }
 
 hipError_t launch_square_pair(float* D, int64_t n, int mode, hipStream_t s) {

@@ -321,8 +321,10 @@ def test_other_phase1_kernels(L, force, monkeypatch):
 def test_topl_many_documents(L, direction, ell):
     """More database rows than one selection workgroup takes (two-pass
     selection): the top-l equals the first l of the full distance row
-    ordered by (distance, index), bit for bit, and its distances match the
-    oracle pair by pair."""
+    ordered by (distance, index) -- bit for bit for D2Q; for SYM within the
+    float32 tie band, since lcemd_distances computes the reverse direction
+    by the swapped-role linear method and lcemd_topl per candidate pair --
+    and its distances match the oracle pair by pair."""
     w = make_workload("text", n=70000, B=3, v=3000)
     ctx = _ctx(L, w)
     say(f"[gpu] top-{ell} {direction} over n=70000 (two-pass selection)")
@@ -334,8 +336,11 @@ def test_topl_many_documents(L, direction, ell):
         row = full[b].astype(np.float64).copy()
         row[excl + b] = np.inf
         order = np.lexsort((np.arange(row.size), row))[:ell]
-        assert np.array_equal(idx[b], order), b
-        assert np.array_equal(dist[b], full[b][order]), b
+        if direction == "d2q":
+            assert np.array_equal(idx[b], order), b
+            assert np.array_equal(dist[b], full[b][order]), b
+        else:
+            P.check_topl(idx[b], dist[b], row, ell, f"query {b}")
         qc, qw = w.queries.row(b)
         for j in range(0, ell, max(1, ell // 8)):
             o = orc.pair(qc, qw, int(idx[b, j]), "act", 4, direction)
