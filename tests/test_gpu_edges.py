@@ -1,0 +1,154 @@
+"""Degenerate and boundary cases through the C-ABI, against closed forms and
+the float64 oracle: single-word histograms, a one-histogram database,
+queries of the maximum length, k beyond the histogram length, embedding
+widths that are not multiples of the padding, and skewed weights."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import emd_oracle as O
+from synth.generators import CSR
+import parity as P
+
+pytestmark = pytest.mark.gpu
+
+MEASURES = [("rwmd", 1), ("omr", 1), ("act", 1), ("act", 3), ("ict", 1)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_02091_amd import lcemd
+
+    lcemd.load_library()
+    return lcemd
+
+
+def _csr(rows):
+    """rows: list of (cols, weights) with ascending distinct cols."""
+    ptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(c) for c, _ in rows])
+    col = np.concatenate([np.asarray(c, dtype=np.int32) for c, _ in rows])
+    val = np.concatenate([np.asarray(w, dtype=np.float64) / np.sum(w) for _, w in rows]).astype(np.float32)
+    return CSR(ptr, col, val)
+
+
+def test_single_word_histograms_are_word_distances(L):
+    """One word on each side: every measure moves all mass along the single
+    edge, so it equals the Euclidean distance of the two words (both
+    directions, SYM)."""
+    rng = np.random.default_rng(21)
+    V = rng.standard_normal((50, 7)).astype(np.float32)
+    db = _csr([([i], [1.0]) for i in range(0, 50, 3)])
+    q = _csr([([i], [1.0]) for i in (1, 3, 49)])
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    want = np.linalg.norm(V[q.col].astype(np.float64)[:, None, :] - V[db.col].astype(np.float64)[None], axis=2)
+    for method, k in MEASURES:
+        for d in ("d2q", "q2d", "sym"):
+            say(f"[gpu] single words {method} k={k} {d}")
+            g = ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction=d)
+            P.assert_distances(g, want, f"{method} {d}")
+            assert g[1, 1] == 0.0  # query word 3 is database row 1's word
+
+
+def test_one_histogram_database(L):
+    rng = np.random.default_rng(22)
+    V = rng.standard_normal((30, 16)).astype(np.float32)
+    db = _csr([([2, 5, 11, 29], [0.1, 0.2, 0.3, 0.4])])
+    q = _csr([([1, 5], [1.0, 3.0]), ([0, 2, 5, 11, 29], [1.0, 1.0, 2.0, 3.0, 4.0])])
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    orc = O.Oracle(V, db.rowptr, db.col, db.val)
+    for method, k in MEASURES:
+        o = orc.matrix(q.rowptr, q.col, q.val, method, k, "sym")
+        P.assert_distances(ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="sym"), o, method)
+        idx, dist = ctx.topl(q.rowptr, q.col, q.val, 1, method=method, k=k, direction="sym")
+        assert idx.ravel().tolist() == [0, 0]
+        P.assert_distances(dist[:, 0], o[:, 0], method)
+
+
+@pytest.mark.parametrize("m", [1, 5, 37])
+def test_embedding_widths(L, m):
+    """Widths far from the 64-dim padding (one slice, partial float4 groups)."""
+    rng = np.random.default_rng(23 + m)
+    v = 400
+    V = rng.standard_normal((v, m)).astype(np.float32)
+    rows = []
+    for _ in range(40):
+        h = int(rng.integers(1, 30))
+        cols = np.sort(rng.choice(v, h, replace=False))
+        rows.append((cols, rng.random(h) + 0.05))
+    db = _csr(rows[:32])
+    q = _csr(rows[32:])
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    orc = O.Oracle(V, db.rowptr, db.col, db.val)
+    for method, k in MEASURES:
+        say(f"[gpu] m={m} {method} k={k}")
+        o = orc.matrix(q.rowptr, q.col, q.val, method, k, "sym")
+        P.assert_distances(ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="sym"), o,
+                           f"m={m} {method}")
+
+
+def test_k_beyond_histogram_length_is_ict(L):
+    """ACT with k at least the query length takes every destination: ICT
+    (Alg. 3 with k_eff = h)."""
+    rng = np.random.default_rng(24)
+    V = rng.standard_normal((200, 12)).astype(np.float32)
+    cols = [np.sort(rng.choice(200, int(rng.integers(2, 9)), replace=False)) for _ in range(30)]
+    rows = [(c, rng.random(c.size) + 0.1) for c in cols]
+    db = _csr(rows[:24])
+    q = _csr(rows[24:])
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    ict = ctx.distances(q.rowptr, q.col, q.val, method="ict", direction="d2q")
+    for k in (8, 16, 64):
+        g = ctx.distances(q.rowptr, q.col, q.val, method="act", k=k, direction="d2q")
+        P.assert_distances(g, ict.astype(np.float64), f"k={k}")
+
+
+def test_maximum_length_queries(L):
+    """Queries of LCEMD_MAX_HIST words (every word of a 1,024-word
+    vocabulary) against short and long database rows."""
+    rng = np.random.default_rng(25)
+    v = L.MAX_HIST
+    V = rng.standard_normal((v, 8)).astype(np.float32)
+    cols = [np.sort(rng.choice(v, h, replace=False)) for h in (1, 40, 700, 1024)]
+    rows = [(c, rng.random(c.size) + 0.05) for c in cols]
+    db = _csr(rows)
+    q = _csr([(np.arange(v), rng.random(v) + 0.05), (np.arange(0, v, 2), rng.random(v // 2) + 0.05)])
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    orc = O.Oracle(V, db.rowptr, db.col, db.val)
+    for method, k in (("rwmd", 1), ("act", 4), ("ict", 1)):
+        say(f"[gpu] 1024-word queries {method} k={k}")
+        o = orc.matrix(q.rowptr, q.col, q.val, method, k, "sym")
+        P.assert_distances(ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="sym"), o,
+                           f"max length {method}")
+
+
+def test_skewed_weights(L):
+    """One word carries almost all the mass: capacity cuts after the first
+    entry, long walks for the rest."""
+    rng = np.random.default_rng(26)
+    V = rng.standard_normal((300, 10)).astype(np.float32)
+    rows = []
+    for _ in range(36):
+        h = int(rng.integers(3, 40))
+        cols = np.sort(rng.choice(300, h, replace=False))
+        w = np.full(h, 1e-4)
+        w[int(rng.integers(h))] = 1.0
+        rows.append((cols, w))
+    db = _csr(rows[:30])
+    q = _csr(rows[30:])
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    orc = O.Oracle(V, db.rowptr, db.col, db.val)
+    for method, k in MEASURES:
+        o = orc.matrix(q.rowptr, q.col, q.val, method, k, "sym")
+        P.assert_distances(ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="sym"), o,
+                           f"skewed {method}")
