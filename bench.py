@@ -188,6 +188,24 @@ def image_section(a, lcemd):
             rec["phase2_hbm_frac"] = gbs * 1e9 / HBM_PEAK
         res[f"act{k}"] = rec
         print(f"[bench] image ACT k={k}: {dt:.3f} s", file=sys.stderr, flush=True)
+    # the full symmetric matrix (the reverse direction by the swapped-role
+    # linear method), device-resident queries and output
+    import torch
+
+    dev = torch.device("cuda:0")
+    qd = [torch.from_numpy(x).to(dev) for x in (q.rowptr, q.col, q.val)]
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    D = ctx.distances(*qd, method="act", k=2, direction="sym")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    ph = {p["name"]: p["ms"] for p in ctx.profile_get()}
+    ctx.profile(False)
+    res["full_sym_matrix_act2"] = {"shape": list(D.shape), "seconds": dt, "distances_per_s": B * n / dt,
+                                   "phase_ms": ph}
+    del D
+    print(f"[bench] image full SYM matrix ACT k=2: {dt:.3f} s", file=sys.stderr, flush=True)
     ctx.close()
     return res
 
