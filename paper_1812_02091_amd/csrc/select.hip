@@ -32,8 +32,7 @@ __device__ __forceinline__ float unpack_f(uint64_t k) {
 }
 
 // Ascending bitonic sort of N (power of two) keys in LDS by all threads.
-template <int N>
-__device__ void bitonic_sort(uint64_t* buf) {
+__device__ void bitonic_sort(uint64_t* buf, int N) {
   for (int k = 2; k <= N; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int i = threadIdx.x; i < N / 2; i += kThreads) {
@@ -53,19 +52,24 @@ __device__ void bitonic_sort(uint64_t* buf) {
 
 // Threshold selection of the L smallest keys of one part of a row.  The
 // buffer holds the best L keys found so far (sorted, at the front) followed
-// by unsorted newcomers; a key enters only if it beats the L-th best at the
-// last compaction, so after the first few thousand keys almost nothing is
-// inserted and the pass runs at the speed of the coalesced reads.  A
-// compaction (bitonic sort of the buffer) runs when the next round of reads
-// could overflow it.  Keys are unique (row index in the low bits), so the
-// result is the exact L smallest in (distance, index) order.
+// by unsorted newcomers; a key enters only if it beats the threshold, so
+// after the first round almost nothing is inserted and the pass runs at the
+// speed of the coalesced reads.  The first threshold is the L-th smallest of
+// the first round's per-thread minima (at least L keys lie at or below it,
+// so every one of the L smallest does); later ones are the L-th best at a
+// compaction, a bitonic sort of the occupied front of the buffer, which runs
+// when the next round could overflow it.  Keys are unique (row index in the
+// low bits), so the result is the exact L smallest in (distance, index)
+// order.
 constexpr int kSelBuf = 4096;
 constexpr int kSelPer = 8;                      // keys per thread per round
 constexpr int kSelRound = kSelPer * kThreads;   // 2048
 constexpr int64_t kSelPart = 32768;             // keys per workgroup in the first pass
 
 __device__ __forceinline__ void sel_compact(uint64_t* buf, int* cnt, uint64_t* thr, int L) {
-  bitonic_sort<kSelBuf>(buf);  // entries at or past *cnt are ~0 and stay at the back
+  int N = 2;
+  while (N < *cnt) N <<= 1;
+  bitonic_sort(buf, N);  // entries at or past *cnt are ~0 and stay at the back
   const int old = *cnt, keep = min(old, L);
   __syncthreads();
   for (int i = keep + (int)threadIdx.x; i < old; i += kThreads) buf[i] = ~0ull;
@@ -85,6 +89,7 @@ __global__ __launch_bounds__(kThreads) void k_select(const void* __restrict__ ke
                                                      int64_t exclude_base, int64_t part_len,
                                                      uint64_t* __restrict__ out) {
   __shared__ uint64_t buf[kSelBuf];
+  __shared__ uint64_t mins[kThreads];
   __shared__ int cnt;
   __shared__ uint64_t thr;
   const int64_t ri = blockIdx.x, part = blockIdx.y;
@@ -114,9 +119,22 @@ __global__ __launch_bounds__(kThreads) void k_select(const void* __restrict__ ke
         else if (u != excl) kk[e] = pack_s(kf[u], (uint32_t)u);
       }
     }
+    uint64_t t_use = t;
+    if (base == lo && L <= kThreads) {
+      // first round: threshold = the L-th smallest per-thread minimum, + 1
+      // so that it admits itself (keys are unique; ~0 if fewer than L)
+      uint64_t m = ~0ull;
+#pragma unroll
+      for (int e = 0; e < kSelPer; ++e) m = kk[e] < m ? kk[e] : m;
+      mins[threadIdx.x] = m;
+      __syncthreads();
+      bitonic_sort(mins, kThreads);
+      t_use = mins[L - 1] == ~0ull ? ~0ull : mins[L - 1] + 1;
+    }
 #pragma unroll
     for (int e = 0; e < kSelPer; ++e)
-      if (kk[e] < t) buf[atomicAdd(&cnt, 1)] = kk[e];
+      if (kk[e] < t_use) buf[atomicAdd(&cnt, 1)] = kk[e];
+    if (base == lo && threadIdx.x == 0) thr = t_use;
     __syncthreads();
   }
   sel_compact(buf, &cnt, &thr, L);
@@ -173,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize_sym(
     buf[i] = kk;
   }
   __syncthreads();
-  bitonic_sort<kSelectBuf>(buf);
+  bitonic_sort(buf, kSelectBuf);
   for (int i = threadIdx.x; i < L; i += kThreads) {
     const uint64_t kk = buf[i];
     idx[b * L + i] = kk == ~0ull ? -1 : (int64_t)(uint32_t)kk;
