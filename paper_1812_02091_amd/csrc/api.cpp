@@ -906,23 +906,22 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
     int* dflags;
     if ((rc = wsget(c, "sym_rows", (size_t)B, drows)) || (rc = wsget(c, "sym_flags", (size_t)B, dflags))) return rc;
     std::vector<int> hflags;
+    bool first = true;
     while (!rows.empty()) {
       const int64_t R = (int64_t)rows.size();
       const int64_t use = std::min<int64_t>(Lp, avail);
       const bool exhaustive = use >= avail;
       const int64_t cld = exhaustive ? use : use + 1;
-      if (cld > kSelectBuf / 2) {
-        // too many candidates for the selection buffer: evaluate Q2D for
-        // every row of the remaining queries
+      if (cld > kSelectBuf / 2 || (!first && R >= 8 && R * 8 > B)) {
+        // too many candidates for the selection buffer, or the certificate
+        // failed for many queries (at least 8 and an eighth of the batch:
+        // measures whose two directions differ widely, such as RWMD): the
+        // whole Q2D matrix by the swapped-role linear method, SYM = max, and
+        // the remaining rows selected from it
         float* q2 = nullptr;
         if ((rc = wsget(c, "q2d_full", (size_t)B * n, q2))) return rc;
-        for (int64_t i = 0; i < R; ++i) {
-          P1Args a = base_args(c, Q, o);
-          a.q0 = rows[i];
-          a.npairs = n;
-          if ((rc = run_pairs(c, Q, o, a, q2 + (int64_t)rows[i] * n, n, n))) return rc;
-          HIPCHK(c, launch_max_inplace(d2q + (int64_t)rows[i] * n, q2 + (int64_t)rows[i] * n, n, c->stream));
-        }
+        if ((rc = run_q2d_lc(c, Q, o, q2, n))) return rc;
+        HIPCHK(c, launch_max_inplace(d2q, q2, B * n, c->stream));
         HIPCHK(c, hipMemcpyAsync(drows, rows.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, c->stream));
         uint64_t* cand;
         if ((rc = wsget(c, "cand", (size_t)R * l, cand))) return rc;
@@ -953,6 +952,7 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
         if (hflags[i]) again.push_back(rows[i]);
       rows.swap(again);
       Lp *= 4;
+      first = false;
     }
   }
   if (!Q.device) {
