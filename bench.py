@@ -211,6 +211,38 @@ def image_section(a, lcemd):
     return res
 
 
+def measures_section(a, lcemd):
+    """The paper's other measures on the text and image workloads (symmetric
+    top-16 over the whole query batch, device-resident queries): RWMD, OMR
+    (Alg. 1), ACT k=4 and ICT (Alg. 2), next to the headline ACT k=16."""
+    import torch
+
+    from synth import make_workload
+
+    dev = torch.device("cuda:0")
+    res = {}
+    for name in ("text", "image"):
+        w = make_workload(name)
+        ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
+        qs = w.queries
+        q = [torch.from_numpy(x).to(dev) for x in (qs.rowptr, qs.col, qs.val)]
+        small = qs.take([0, 1])
+        out = {}
+        for method, k in (("rwmd", 1), ("omr", 1), ("act", 4), ("ict", 1)):
+            ctx.topl(small.rowptr, small.col, small.val, 16, method=method, k=k, direction="sym")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx.topl(*q, 16, method=method, k=k, direction="sym")
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            out[f"{method}{k}" if method == "act" else method] = {"seconds": dt,
+                                                                   "distances_per_s": qs.n * w.db.n / dt}
+            print(f"[bench] {name} {method} k={k}: {dt:.3f} s", file=sys.stderr, flush=True)
+        res[name] = {"queries": qs.n, "database": w.db.n, "sym_top16": out}
+        ctx.close()
+    return res
+
+
 def selfjoin_section(a, lcemd):
     """All-pairs protocol of Sec. 5 at the MNIST training-set shape: every one
     of 60,000 image histograms against all 60,000 (itself excluded), ACT
@@ -523,6 +555,7 @@ def main():
     ctx.close()
     image = None if a.no_big else image_section(a, lcemd)
     selfjoin = None if a.no_big else selfjoin_section(a, lcemd)
+    measures = None if a.no_big else measures_section(a, lcemd)
     dense = None if a.no_big else dense_section(a, lcemd)
     big = None if a.no_big else big_workload(a, lcemd)
 
@@ -551,6 +584,7 @@ def main():
         "counters": counters,
         "image": image,
         "selfjoin": selfjoin,
+        "measures": measures,
         "image_bg": dense,
         "text_1M": big,
     }
