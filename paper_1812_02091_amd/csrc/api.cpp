@@ -372,6 +372,10 @@ P1Args base_args(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o) { return base
 // out[b * ld + u].
 int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
   int KT = table_depth(o, Q.hmax);
+  // ICT: the tables hold up to KT entries per row, but the lists of phase 1
+  // stop at kIctList (a row needs a few entries before its capacities cover
+  // the word's largest weight, Lemma 1); deeper rows are redone exactly
+  bool full_lists = o->method != LCEMD_ICT;
   int prec = o->precision;
   const size_t per_q = (size_t)db.v_used * sizeof(float2);
   int* ovf;
@@ -401,7 +405,8 @@ int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, 
     a.fix_cap = kFixCap;
     int64_t H = Q.hptr[q0 + nq] - Q.hptr[q0];
     if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)db.v_used * (double)H * (double)c->m))) return rc;
-    if ((rc = p1_launch(c, a, P1_TABLE, prec, KT, Q.hmax, Q.hmax))) return rc;
+    const int list_depth = full_lists ? KT : std::min(KT, kIctList);
+    if ((rc = p1_launch(c, a, P1_TABLE, prec, list_depth, Q.hmax, Q.hmax))) return rc;
     if ((rc = prof_end(c))) return rc;
     {
       int h_ovf = 0, h_fix = 0;
@@ -420,8 +425,14 @@ int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, 
         // a row needed more list entries than the kernel keeps: redo the tile
         // with float32 keys, and for ICT with full-depth tables
         ++c->fallbacks;
-        if (prec != LCEMD_FP32) prec = LCEMD_FP32;
-        else KT = Q.hmax;
+        if (prec != LCEMD_FP32) {
+          prec = LCEMD_FP32;
+        } else {
+          // the exact redo of ICT's short lists already reaches KT entries:
+          // an overflow there needs the full depth
+          full_lists = true;
+          KT = Q.hmax;
+        }
         continue;
       }
     }

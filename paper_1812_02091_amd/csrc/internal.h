@@ -24,6 +24,9 @@ constexpr int kSelectBuf = 2048; // LDS slots of the selection sort
 // phase-1 kernel variant; longer ones (up to LCEMD_MAX_HIST) run on float32
 // variants sized for them.
 constexpr int kSegShort = 512;
+// ICT's phase-1 lists stop here (its tables hold more); the few rows whose
+// capacities do not yet cover the word's largest weight are redone exactly.
+constexpr int kIctList = 16;
 // The keys kernel for segments longer than kSegShort keeps its rows of keys
 // in device memory: one region of kRows x (LCEMD_MAX_HIST + 4) floats per
 // workgroup of a launch, launches of at most kDeepSlots workgroups.

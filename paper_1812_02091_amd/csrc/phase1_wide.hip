@@ -720,7 +720,16 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     // shortfall after the exact re-sort is a rounding residue of the
     // capacity sum, which the last entry absorbs
     if (!covered && sm.rcut[row]) covered = true;
-    if (!covered && D < h && a.overflow) a.overflow[0] = 1;
+    // rows redone exactly by k_fix_rows (table modes, while their list has
+    // room; otherwise the launch reports overflow): a list that ran out
+    // before the row's bound was covered (an ICT row deeper than the list;
+    // the table may hold up to KT entries), or a cut that is not certified
+    const bool can_redo = MODE != P1_PAIR && a.fix_list != nullptr;
+    bool redo = false;
+    if (!covered && D < h) {
+      if (can_redo) redo = true;
+      else if (a.overflow) a.overflow[0] = 1;
+    }
     // a candidate left out of a full list has a key >= rdrop - half a band
     // (bf16; exact keys for float32): the used entries must all be nearer
     if (QK && D > 0 && sm.rdrop[row] < INFINITY && a.overflow) {
@@ -734,12 +743,14 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
         certified = last_key < sm.rdrop[row] - half_band - 1e-6f * (sm.rvn[row] + sm.qmax * sm.qmax);
       }
       if (!certified) {
-        // redo this row exactly (k_fix_rows) unless the list of such rows is full
-        int slot = a.fix_cap;
-        if (MODE != P1_PAIR && a.fix_list) slot = atomicAdd(a.fix_count, 1);
-        if (slot < a.fix_cap) a.fix_list[slot] = out_row0 + row;
+        if (can_redo) redo = true;
         else a.overflow[0] = 1;
       }
+    }
+    if (redo) {
+      const int slot = atomicAdd(a.fix_count, 1);
+      if (slot < a.fix_cap) a.fix_list[slot] = out_row0 + row;
+      else if (a.overflow) a.overflow[0] = 1;
     }
     if constexpr (MODE == P1_TABLE) {
       const int64_t flat = out_row0 + row;

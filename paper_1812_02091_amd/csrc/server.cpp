@@ -189,7 +189,10 @@ int issue(lcemd_server* s, Lane& L) {
     a.fix_count = L.ints + 9;
     a.fix_list = L.fixl;
     a.fix_cap = kFixCapLane;
-    if ((rc = p1_launch(c, a, P1_TABLE, s->prec, s->KT, LCEMD_SERVE_MAX_HIST, LCEMD_SERVE_MAX_HIST))) break;
+    // ICT lists stop at 16 entries as in lcemd_topl; deeper rows go to the
+    // exact redo below (tables hold s->KT entries)
+    const int list_depth = s->cfg.method == LCEMD_ICT ? std::min(s->KT, kIctList) : s->KT;
+    if ((rc = p1_launch(c, a, P1_TABLE, s->prec, list_depth, LCEMD_SERVE_MAX_HIST, LCEMD_SERVE_MAX_HIST))) break;
     HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixBlocks, L.stream));
     HIPCHK(c, launch_phase2_persistent(c->xptr, c->xcv, c->n, c->xperm, L.ZW, zw_pitch(s->B), s->KT, s->B, L.nq,
                                        L.d2q, c->n, L.ctr + 8, L.stream));
