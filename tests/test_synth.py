@@ -71,3 +71,28 @@ def test_distinct_words_independent_of_threads():
     for r in range(0, 3000, 13):
         c = a[1][a[0][r]:a[0][r + 1]]
         assert c.size == lengths[r] and np.all(np.diff(c) > 0) and c.max() < 300
+
+
+def test_image_background_histograms():
+    """Images with their background: every histogram has all 784 pixels, rows
+    sum to 1, the foreground draws are those of the same generator without
+    background, and the workload is seeded (same arrays on a second build)."""
+    import numpy as np
+
+    from synth import make_workload
+    from synth.generators import blob_histograms, _rng, STREAM_DB
+
+    w = make_workload("image-bg", n=50, B=3)
+    assert np.all(np.diff(w.db.rowptr) == 784) and np.all(np.diff(w.queries.rowptr) == 784)
+    sums = np.add.reduceat(w.db.val.astype(np.float64), w.db.rowptr[:-1])
+    assert np.allclose(sums, 1.0, atol=1e-5) and np.all(w.db.val > 0)
+    again = make_workload("image-bg", n=50, B=3)
+    assert np.array_equal(w.db.val, again.db.val) and np.array_equal(w.queries.val, again.queries.val)
+    sparse = blob_histograms(_rng(5, STREAM_DB), 50)
+    dense = w.db
+    for r in range(0, 50, 7):
+        cols = sparse.col[sparse.rowptr[r]:sparse.rowptr[r + 1]]
+        d = dense.val[dense.rowptr[r]:dense.rowptr[r + 1]]
+        bg = np.setdiff1d(np.arange(784), cols)
+        # background pixels share one (smallest) weight; disc pixels are heavier
+        assert np.allclose(d[bg], d[bg][0]) and np.all(d[cols] > d[bg][0])
