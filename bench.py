@@ -238,7 +238,23 @@ def measures_section(a, lcemd):
             out[f"{method}{k}" if method == "act" else method] = {"seconds": dt,
                                                                    "distances_per_s": qs.n * w.db.n / dt}
             print(f"[bench] {name} {method} k={k}: {dt:.3f} s", file=sys.stderr, flush=True)
-        res[name] = {"queries": qs.n, "database": w.db.n, "sym_top16": out}
+        # one direction (D2Q), RWMD against ACT with one phase-2 iteration
+        # (k=2): Sec. 5 compares their costs (phase 1 dominates at m = 300,
+        # phase 2 at m = 2)
+        d2q = {}
+        for method, k in (("rwmd", 1), ("act", 2)):
+            ctx.topl(small.rowptr, small.col, small.val, 16, method=method, k=k, direction="d2q")
+            ctx.profile(True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx.topl(*q, 16, method=method, k=k, direction="d2q")
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            ph = {p["name"]: p["ms"] for p in ctx.profile_get()}
+            ctx.profile(False)
+            d2q[f"{method}{k}" if method == "act" else method] = {"seconds": dt, "phase_ms": ph}
+        d2q["act2_over_rwmd"] = d2q["act2"]["seconds"] / d2q["rwmd"]["seconds"]
+        res[name] = {"queries": qs.n, "database": w.db.n, "sym_top16": out, "d2q_top16": d2q}
         ctx.close()
     return res
 
