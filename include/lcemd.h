@@ -97,6 +97,8 @@ extern "C" {
 #define LCEMD_PTR_DEVICE 0x1u  /* array arguments are device pointers */
 #define LCEMD_NORMALIZE 0x2u   /* load_database: renormalise rows (float64 sums) */
 #define LCEMD_L2_NORMALIZE 0x4u /* load_embeddings: scale rows to unit L2 norm */
+#define LCEMD_MAKE_BF16 0x8u    /* load_embeddings: build the bfloat16 copy now */
+#define LCEMD_MAKE_FP8 0x10u    /* load_embeddings: build the fp8 copy now */
 
 /* limits */
 #define LCEMD_MAX_HIST 1024 /* max non-zeros of one query or database row (dense
@@ -152,8 +154,10 @@ const char* lcemd_last_error(const lcemd_ctx* ctx);
 /* Load the vocabulary embeddings V: v rows of m float32 (row-major, finite),
  * the coordinates of Sec. 4's matrix V.  Replaces earlier embeddings (and
  * drops a loaded database).  Builds the device-side padded copy, the row
- * norms (accumulated in float64) and, on request at query time, bfloat16 /
- * fp8 copies.  Flags: LCEMD_PTR_DEVICE, LCEMD_L2_NORMALIZE.
+ * norms (accumulated in float64) and the bfloat16 / fp8 copies: at load
+ * with LCEMD_MAKE_BF16 / LCEMD_MAKE_FP8, else at the first call that asks
+ * for that precision (the copies are the same either way).  Flags:
+ * LCEMD_PTR_DEVICE, LCEMD_L2_NORMALIZE, LCEMD_MAKE_BF16, LCEMD_MAKE_FP8.
  * Limits: 1 <= v < 2^31, 1 <= m <= 4096. */
 int lcemd_load_embeddings(lcemd_ctx* ctx, const float* V, int64_t v, int32_t m,
                           uint32_t flags);

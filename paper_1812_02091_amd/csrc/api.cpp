@@ -667,6 +667,8 @@ int lcemd_load_embeddings(lcemd_ctx* c, const float* V, int64_t v, int32_t m, ui
   if (!V) return fail(c, LCEMD_E_INVALID_ARG, "V must not be NULL");
   if (v < 1 || v >= (int64_t(1) << 31)) return fail(c, LCEMD_E_INVALID_ARG, "v out of range");
   if (m < 1 || m > 4096) return fail(c, LCEMD_E_INVALID_ARG, "m out of range (1..4096)");
+  if (flags & ~(LCEMD_PTR_DEVICE | LCEMD_L2_NORMALIZE | LCEMD_MAKE_BF16 | LCEMD_MAKE_FP8))
+    return fail(c, LCEMD_E_INVALID_ARG, "unknown flags");
   (void)hipSetDevice(c->device);
   const bool dev = flags & LCEMD_PTR_DEVICE;
   if (!dev) {
@@ -693,6 +695,9 @@ int lcemd_load_embeddings(lcemd_ctx* c, const float* V, int64_t v, int32_t m, ui
   c->v = v;
   c->m = m;
   c->m_pad = m_pad;
+  if (flags & LCEMD_MAKE_BF16 && (rc = ensure_precision(c, LCEMD_BF16))) return rc;
+  if (flags & LCEMD_MAKE_FP8 && (rc = ensure_precision(c, LCEMD_FP8))) return rc;
+  if (flags & (LCEMD_MAKE_BF16 | LCEMD_MAKE_FP8)) HIPCHK(c, hipStreamSynchronize(c->stream));
   return LCEMD_OK;
 }
 

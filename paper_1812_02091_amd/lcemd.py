@@ -20,7 +20,7 @@ E_INVALID_ARG, E_BAD_CSR, E_NOT_LOADED, E_OOM, E_HIP, E_UNSUPPORTED, E_CAPACITY,
 RWMD, OMR, ACT, ICT = 0, 1, 2, 3
 D2Q, Q2D, SYM = 0, 1, 2
 FP32, BF16, FP8 = 0, 1, 2
-PTR_DEVICE, NORMALIZE, L2_NORMALIZE = 0x1, 0x2, 0x4
+PTR_DEVICE, NORMALIZE, L2_NORMALIZE, MAKE_BF16, MAKE_FP8 = 0x1, 0x2, 0x4, 0x8, 0x10
 MAX_HIST, MAX_L, MAX_K = 1024, 1024, 512
 SERVE_MAX_HIST = 512
 
@@ -201,12 +201,19 @@ class Context:
             self._check(self.lib.lcemd_use_own_stream(self.h))
 
     # ---- loads ----
-    def load_embeddings(self, V, l2_normalize: bool = False):
+    def load_embeddings(self, V, l2_normalize: bool = False, precisions=()):
+        """precisions: reduced-precision copies to build now ("bf16", "fp8")
+        rather than at the first call that asks for them."""
         dev = _device_mode(V)
         self._sync_stream(dev)
         a = _Arg(V, np.float32, dev)
         v, m = a.obj.shape
+        make = {"bf16": MAKE_BF16, "fp8": MAKE_FP8}
         flags = (PTR_DEVICE if dev else 0) | (L2_NORMALIZE if l2_normalize else 0)
+        for p in precisions:
+            if p not in make:
+                raise ValueError(f"precision {p!r}: one of {sorted(make)}")
+            flags |= make[p]
         self._check(self.lib.lcemd_load_embeddings(self.h, C.c_void_p(a.ptr), v, m, flags))
 
     def load_database(self, rowptr, col, val, normalize: bool = False):
@@ -406,10 +413,11 @@ def check_histograms(rowptr, col, val, v: int, require_normalized: bool = True):
     return rc, msg.value.decode()
 
 
-def open_context(V, db_rowptr, db_col, db_val, device: int = 0, l2_normalize: bool = False) -> Context:
+def open_context(V, db_rowptr, db_col, db_val, device: int = 0, l2_normalize: bool = False,
+                 precisions=()) -> Context:
     """Context with embeddings and database loaded."""
     ctx = Context(device)
-    ctx.load_embeddings(V, l2_normalize=l2_normalize)
+    ctx.load_embeddings(V, l2_normalize=l2_normalize, precisions=precisions)
     ctx.load_database(db_rowptr, db_col, db_val)
     ctx.n = int(db_rowptr.shape[0] - 1)
     return ctx

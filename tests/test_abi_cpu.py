@@ -50,6 +50,8 @@ def test_header_constants_match_binding():
     assert const("LCEMD_PTR_DEVICE") == L.PTR_DEVICE
     assert const("LCEMD_MAX_HIST") == L.MAX_HIST and const("LCEMD_MAX_L") == L.MAX_L
     assert const("LCEMD_SERVE_MAX_HIST") == L.SERVE_MAX_HIST
+    assert const("LCEMD_MAKE_BF16") == L.MAKE_BF16 and const("LCEMD_MAKE_FP8") == L.MAKE_FP8
+    assert const("LCEMD_L2_NORMALIZE") == L.L2_NORMALIZE and const("LCEMD_NORMALIZE") == L.NORMALIZE
 
 
 def _has_gpu():

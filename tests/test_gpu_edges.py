@@ -152,3 +152,22 @@ def test_skewed_weights(L):
         o = orc.matrix(q.rowptr, q.col, q.val, method, k, "sym")
         P.assert_distances(ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="sym"), o,
                            f"skewed {method}")
+
+
+def test_reduced_precision_copies_built_at_load(L):
+    """LCEMD_MAKE_BF16 / LCEMD_MAKE_FP8 build the reduced-precision copies at
+    load; the results are those of copies built at the first call that asks."""
+    from synth import make_workload
+
+    w = make_workload("text", n=150, B=5, v=4000)
+    q = (w.queries.rowptr, w.queries.col, w.queries.val)
+    lazy = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val)
+    eager = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, precisions=("bf16", "fp8"))
+    for prec in ("bf16", "fp8"):
+        say(f"[gpu] copies at load, {prec}")
+        for method, k in (("act", 4), ("ict", 1)):
+            i0, d0 = lazy.topl(*q, 8, method=method, k=k, direction="sym", precision=prec)
+            i1, d1 = eager.topl(*q, 8, method=method, k=k, direction="sym", precision=prec)
+            assert np.array_equal(i0, i1) and np.array_equal(d0, d1), (prec, method)
+    with pytest.raises(ValueError):
+        eager.load_embeddings(w.V, precisions=("fp16",))
