@@ -157,7 +157,9 @@ const char* lcemd_last_error(const lcemd_ctx* ctx);
  * norms (accumulated in float64) and the bfloat16 / fp8 copies: at load
  * with LCEMD_MAKE_BF16 / LCEMD_MAKE_FP8, else at the first call that asks
  * for that precision (the copies are the same either way).  Flags:
- * LCEMD_PTR_DEVICE, LCEMD_L2_NORMALIZE, LCEMD_MAKE_BF16, LCEMD_MAKE_FP8.
+ * LCEMD_PTR_DEVICE, LCEMD_L2_NORMALIZE, LCEMD_MAKE_BF16, LCEMD_MAKE_FP8;
+ * other bits are LCEMD_E_INVALID_ARG.  If a copy asked for by a MAKE flag
+ * cannot be allocated (LCEMD_E_OOM), the float32 embeddings stay loaded.
  * Limits: 1 <= v < 2^31, 1 <= m <= 4096. */
 int lcemd_load_embeddings(lcemd_ctx* ctx, const float* V, int64_t v, int32_t m,
                           uint32_t flags);
@@ -166,7 +168,8 @@ int lcemd_load_embeddings(lcemd_ctx* ctx, const float* V, int64_t v, int32_t m,
  * CSR).  Requires embeddings.  Derives the used vocabulary (the union of
  * the database's words, Sec. 2.2) and, per used word, the largest weight
  * any database row gives it (bounds how deep a transfer can go).  Flags:
- * LCEMD_PTR_DEVICE, LCEMD_NORMALIZE.  Limits: n >= 1, at most
+ * LCEMD_PTR_DEVICE, LCEMD_NORMALIZE (other bits: LCEMD_E_INVALID_ARG).
+ * Limits: n >= 1, at most
  * LCEMD_MAX_HIST non-zeros per row. */
 int lcemd_load_database(lcemd_ctx* ctx, const int64_t* rowptr, const int32_t* col,
                         const float* val, int64_t n, uint32_t flags);

@@ -683,15 +683,22 @@ int lcemd_load_embeddings(lcemd_ctx* c, const float* V, int64_t v, int32_t m, ui
   if ((rc = dalloc(c, c->vnorm, (size_t)v, "row norms"))) return rc;
   const float* src = V;
   float* tmp = nullptr;
+  hipError_t e = hipSuccess;
   if (!dev) {
     if ((rc = dalloc(c, tmp, (size_t)v * m, "embedding staging"))) return rc;
-    HIPCHK(c, hipMemcpyAsync(tmp, V, sizeof(float) * v * m, hipMemcpyHostToDevice, c->stream));
+    e = hipMemcpyAsync(tmp, V, sizeof(float) * v * m, hipMemcpyHostToDevice, c->stream);
     src = tmp;
   }
-  HIPCHK(c, launch_prep_embeddings(src, v, m, m_pad, (flags & LCEMD_L2_NORMALIZE) ? 1 : 0, c->V,
-                                   c->vnorm, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (tmp) (void)hipFree(tmp);
+  if (e == hipSuccess)
+    e = launch_prep_embeddings(src, v, m, m_pad, (flags & LCEMD_L2_NORMALIZE) ? 1 : 0, c->V, c->vnorm,
+                               c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (tmp) {
+    if (e != hipSuccess) (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+  }
+  if (e != hipSuccess)
+    return fail(c, LCEMD_E_HIP, "embedding preparation failed: %s", hipGetErrorString(e));
   c->v = v;
   c->m = m;
   c->m_pad = m_pad;
@@ -708,6 +715,7 @@ int lcemd_load_database(lcemd_ctx* c, const int64_t* rowptr, const int32_t* col,
   if (!c->V) return fail(c, LCEMD_E_NOT_LOADED, "load embeddings before the database");
   if (!rowptr || !col || !val) return fail(c, LCEMD_E_INVALID_ARG, "database arrays must not be NULL");
   if (n < 1 || n >= (int64_t(1) << 31)) return fail(c, LCEMD_E_INVALID_ARG, "n out of range");
+  if (flags & ~(LCEMD_PTR_DEVICE | LCEMD_NORMALIZE)) return fail(c, LCEMD_E_INVALID_ARG, "unknown flags");
   (void)hipSetDevice(c->device);
   const bool dev = flags & LCEMD_PTR_DEVICE;
   // host copies (the database is reorganised once, on the host)

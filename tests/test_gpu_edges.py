@@ -171,3 +171,22 @@ def test_reduced_precision_copies_built_at_load(L):
             assert np.array_equal(i0, i1) and np.array_equal(d0, d1), (prec, method)
     with pytest.raises(ValueError):
         eager.load_embeddings(w.V, precisions=("fp16",))
+
+
+def test_unknown_load_flags_rejected(L):
+    """Flag bits the header does not define are LCEMD_E_INVALID_ARG, checked
+    before anything loaded is dropped."""
+    import ctypes as C
+
+    rng = np.random.default_rng(27)
+    V = rng.standard_normal((40, 6)).astype(np.float32)
+    db = _csr([([1, 4, 9], [1.0, 2.0, 3.0]), ([0, 39], [1.0, 1.0])])
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    before = ctx.distances(db.rowptr, db.col, db.val, method="act", k=2, direction="sym")
+    rc = ctx.lib.lcemd_load_embeddings(ctx.h, C.c_void_p(V.ctypes.data), 40, 6, 0x100)
+    assert rc == L.E_INVALID_ARG
+    rc = ctx.lib.lcemd_load_database(ctx.h, C.c_void_p(db.rowptr.ctypes.data), C.c_void_p(db.col.ctypes.data),
+                                     C.c_void_p(db.val.ctypes.data), 2, 0x100)
+    assert rc == L.E_INVALID_ARG
+    after = ctx.distances(db.rowptr, db.col, db.val, method="act", k=2, direction="sym")
+    assert np.array_equal(before, after)
