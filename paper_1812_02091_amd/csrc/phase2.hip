@@ -29,6 +29,7 @@ namespace lcemd {
 
 constexpr int kUnroll = 8;       // non-zeros whose table loads are in flight together
 constexpr int kItemSlots = 16;   // document slots per lane and work item
+static_assert(kItemSlots % 4 == 0, "results are stored four at a time");
 
 // One transfer step of Eq. (6)-(8) against table entry (z, w).
 __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
@@ -156,12 +157,38 @@ __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
     const bool qok = q < nq;
     const float4* Zq = ZP + (qok ? q : nq - 1);
     const int64_t d0 = (item % nd) * kDocs + ds;
-    for (int j = 0; j < kItemSlots; ++j) {
-      const int64_t i = d0 + (int64_t)j * S;
-      if (i >= n) break;
-      const int64_t u = S > 1 ? (int64_t)perm[i] : i;
-      const float c = doc_cost<S == 1>(xptr[u], xptr[u + 1], xcv, Zq, zw_nq, KP, lane, ds * QL);
-      if (qok) out[q * ld + u] = c;
+    if constexpr (S == 1) {
+      // one document at a time for all 64 lanes: each lane's kItemSlots
+      // results are consecutive in its query's row, so they are staged in
+      // the wave's own LDS rows (lane-private slots: no barrier) and written
+      // together, 16-byte stores where aligned
+      __shared__ float st[kThreads / 64][kItemSlots][64];
+      float(*sw)[64] = st[threadIdx.x >> 6];
+      int cnt = 0;
+      for (int j = 0; j < kItemSlots; ++j) {
+        const int64_t i = d0 + j;
+        if (i >= n) break;
+        sw[j][lane] = doc_cost<true>(xptr[i], xptr[i + 1], xcv, Zq, zw_nq, KP, lane, 0);
+        ++cnt;
+      }
+      if (qok && cnt > 0) {
+        float* o = out + q * ld + d0;
+        if (cnt == kItemSlots && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+#pragma unroll
+          for (int t = 0; t < kItemSlots; t += 4)
+            *reinterpret_cast<float4*>(o + t) = make_float4(sw[t][lane], sw[t + 1][lane], sw[t + 2][lane], sw[t + 3][lane]);
+        } else {
+          for (int t = 0; t < cnt; ++t) o[t] = sw[t][lane];
+        }
+      }
+    } else {
+      for (int j = 0; j < kItemSlots; ++j) {
+        const int64_t i = d0 + (int64_t)j * S;
+        if (i >= n) break;
+        const int64_t u = (int64_t)perm[i];
+        const float c = doc_cost<false>(xptr[u], xptr[u + 1], xcv, Zq, zw_nq, KP, lane, ds * QL);
+        if (qok) out[q * ld + u] = c;
+      }
     }
   }
 }
