@@ -56,8 +56,9 @@ def parse():
     return ap.parse_args()
 
 
-def phase1_kernel(method, k, precision):
-    """The phase-1 kernel the library picks for the table (D2Q) pass."""
+def phase1_kernel(method, k, precision, m):
+    """The phase-1 kernel the library picks for the table (D2Q) pass of
+    queries against m-dimensional embeddings."""
     depth = {"rwmd": 1, "omr": 2, "act": k, "ict": 64}[method]
     margin = 0 if precision == "fp32" or depth + 8 > 32 else 8
     kl = 2
@@ -65,6 +66,8 @@ def phase1_kernel(method, k, precision):
         kl *= 2
     prec = 0 if margin == 0 else 1
     if depth + margin <= 32:
+        if prec == 0 and (m + 3) // 4 <= 7:  # float32, one short slice
+            return f"k_phase1_wide_short<0, {kl}, false>"
         return f"k_phase1_wide<0, {kl}, {prec}, false>"
     return "k_phase1_fast<0, 64, 0>" if depth <= 64 else "k_phase1_f32"
 
@@ -512,7 +515,7 @@ def main():
     per_launch_flops = p1["work"] / max(1, p1["launches"])
     achieved = per_launch_flops / (per_launch_ms * 1e-3) if per_launch_ms > 0 else 0.0
     peak = PEAKS.get(a.precision, PEAKS["fp32"])
-    kernel = phase1_kernel(a.method, a.k, a.precision)
+    kernel = phase1_kernel(a.method, a.k, a.precision, w.V.shape[1])
     roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": measured_traffic(kernel, a),
                 "kernel": kernel,
