@@ -65,9 +65,9 @@ def phase1_kernel(method, k, precision, m):
     while kl < depth + margin:
         kl *= 2
     prec = 0 if margin == 0 else 1
+    if prec == 0 and (m + 3) // 4 <= 7 and depth <= 64:  # float32, at most 28 dims: 64-row kernel
+        return f"k_phase1_fast<0, {kl}, 0>"
     if depth + margin <= 32:
-        if prec == 0 and (m + 3) // 4 <= 7:  # float32, one short slice
-            return f"k_phase1_wide_short<0, {kl}, false>"
         return f"k_phase1_wide<0, {kl}, {prec}, false>"
     return "k_phase1_fast<0, 64, 0>" if depth <= 64 else "k_phase1_f32"
 

@@ -184,38 +184,10 @@ __device__ __forceinline__ void slice_fp8(floatx16 (&acc)[4], const uint4 (&a_cu
   }
 }
 
-// Float32 with fewer than 32 real dims (4 m4 <= 28, one slice): lane half
-// lh supplies dims [lh r2, lh r2 + r2) of the slice (r2 = 2 m4), so r2
-// MFMAs cover it instead of 16.  The dims past the real ones are zero in
-// both operands.
-template <int NT>
-__device__ __forceinline__ void slice_f32_short(floatx16 (&acc)[4], const uint4 (&a_cur)[4],
-                                                const unsigned char* st, int li, int lh, int r2) {
-  const float* af = (const float*)a_cur;
-  const float* bcol = (const float*)(st + li * kStride) + lh * r2;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (j < r2) {
-      float bv[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) bv[t] = bcol[t * (32 * kStride / 4) + j];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[j], bv[t], acc[t], 0, 0, 0);
-    }
-  }
-}
-
-template <int PREC, bool SM>
+template <int PREC>
 __device__ __forceinline__ void slice_mfma(int ntile, floatx16 (&acc)[4], const uint4 (&a_cur)[4],
-                                           const unsigned char* st, int li, int lh, int r2) {
-  if constexpr (SM) {
-    switch (ntile) {
-      case 1: slice_f32_short<1>(acc, a_cur, st, li, lh, r2); break;
-      case 2: slice_f32_short<2>(acc, a_cur, st, li, lh, r2); break;
-      case 3: slice_f32_short<3>(acc, a_cur, st, li, lh, r2); break;
-      default: slice_f32_short<4>(acc, a_cur, st, li, lh, r2); break;
-    }
-  } else if constexpr (PREC == PREC_F32) {
+                                           const unsigned char* st, int li, int lh) {
+  if constexpr (PREC == PREC_F32) {
     switch (ntile) {
       case 1: slice_f32<1>(acc, a_cur, st, li, lh); break;
       case 2: slice_f32<2>(acc, a_cur, st, li, lh); break;
@@ -310,7 +282,7 @@ __device__ __forceinline__ void wide_dots(float (&ex)[KH], const int (&ps)[KH], 
 
 // One work item: (query, 128-row block) in the table modes, (pair, row
 // block) in pair mode.  Returns early (uniformly) for empty items.
-template <int MODE, int KL, int PREC, bool LONG, bool SM>
+template <int MODE, int KL, int PREC, bool LONG>
 __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_raw, int64_t item) {
   // quantised keys everywhere but in the float32 pair mode; EX: float32
   // with quantised keys keeps the exact keys and one more list slot.
@@ -439,23 +411,8 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
   const bool arow_ok = arow < nrows;
   const unsigned char* aptr = base + (size_t)sm.rid[arow] * rowbytes + lh * 64;
 
-  // SM (float32, 4 m4 <= 28): the one slice in the short layout of
-  // slice_f32_short, r2 = 2 m4 dims per lane half
-  const int r2 = SM ? 2 * a.m4 : 16;
   uint4 a_cur[4], a_nxt[4], b_nxt[4];
   auto load_a = [&](int sl) {
-    if constexpr (SM) {
-      // 16 floats from dim lh r2 (8-byte aligned: r2 is even); those past
-      // the first r2 are not used
-      const uint2* p = (const uint2*)(aptr + lh * (r2 * 4 - 64));
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint2 x = arow_ok ? p[2 * i] : make_uint2(0, 0);
-        const uint2 y = arow_ok ? p[2 * i + 1] : make_uint2(0, 0);
-        a_nxt[i] = make_uint4(x.x, x.y, y.x, y.y);
-      }
-      return;
-    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       a_nxt[i] = arow_ok ? *(const uint4*)(aptr + sl * 128 + i * 16) : make_uint4(0, 0, 0, 0);
@@ -510,7 +467,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
         set_b(c0 + kWC);
         load_b(0);
       }
-      slice_mfma<PREC, SM>(ntile, acc, a_cur, sm.u.st, li, lh, r2);
+      slice_mfma<PREC>(ntile, acc, a_cur, sm.u.st, li, lh);
     }
 
     // ---- selection: 64 columns at a time ----
@@ -840,9 +797,10 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
 // from the counter of its XCD (workgroup i runs on XCD i % 8), which walks a
 // contiguous eighth of the items.  No workgroup waits on another; each
 // exits once its counter passes the end of its range.
-template <int MODE, int KL, int PREC, bool LONG, bool SM>
-__device__ __forceinline__ void wide_loop(const P1Args& a, int64_t total, unsigned char* smem_raw,
-                                          int64_t& s_item) {
+template <int MODE, int KL, int PREC, bool LONG>
+__global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a, int64_t total) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int64_t s_item;
   const int xcd = blockIdx.x & 7;
   const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
   while (true) {
@@ -851,32 +809,15 @@ __device__ __forceinline__ void wide_loop(const P1Args& a, int64_t total, unsign
     __syncthreads();
     const int64_t item = s_item;
     if (item >= hi) break;
-    wide_task<MODE, KL, PREC, LONG, SM>(a, smem_raw, item);
+    wide_task<MODE, KL, PREC, LONG>(a, smem_raw, item);
   }
 }
 
 template <int MODE, int KL, int PREC, bool LONG>
-__global__ __launch_bounds__(kThreads, 2) void k_phase1_wide(P1Args a, int64_t total) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int64_t s_item;
-  wide_loop<MODE, KL, PREC, LONG, false>(a, total, smem_raw, s_item);
-}
-
-// float32 with at most 28 dims (4 m4 <= 28): the contraction is one short
-// slice (slice_f32_short)
-template <int MODE, int KL, bool LONG>
-__global__ __launch_bounds__(kThreads, 2) void k_phase1_wide_short(P1Args a, int64_t total) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int64_t s_item;
-  wide_loop<MODE, KL, PREC_F32, LONG, true>(a, total, smem_raw, s_item);
-}
-
-template <int MODE, int KL, int PREC, bool LONG, bool SM>
 static hipError_t launch_wide_one(const P1Args& a, hipStream_t s) {
-  static_assert(!SM || PREC == PREC_F32, "the short slice is a float32 layout");
   constexpr bool QK = PREC != PREC_F32 || MODE != P1_PAIR;
   const size_t shmem = sizeof(WideSmem<KL, PREC, QK, PREC == PREC_F32 && QK, LONG ? kSegLong : kSeg>);
-  const void* fn = SM ? (const void*)k_phase1_wide_short<MODE, KL, LONG> : (const void*)k_phase1_wide<MODE, KL, PREC, LONG>;
+  const void* fn = (const void*)k_phase1_wide<MODE, KL, PREC, LONG>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
   if (e != hipSuccess) return e;
   int64_t total;
@@ -892,29 +833,26 @@ static hipError_t launch_wide_one(const P1Args& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int grid = persistent_grid(fn, kThreads, shmem, total);
   if (grid <= 0) return hipErrorInvalidConfiguration;
-  if constexpr (SM)
-    hipLaunchKernelGGL((k_phase1_wide_short<MODE, KL, LONG>), dim3(grid), dim3(kThreads), shmem, s, a, total);
-  else
-    hipLaunchKernelGGL((k_phase1_wide<MODE, KL, PREC, LONG>), dim3(grid), dim3(kThreads), shmem, s, a, total);
+  hipLaunchKernelGGL((k_phase1_wide<MODE, KL, PREC, LONG>), dim3(grid), dim3(kThreads), shmem, s, a, total);
   return hipGetLastError();
 }
 
-template <int MODE, int PREC, bool LONG, bool SM>
+template <int MODE, int PREC, bool LONG>
 static hipError_t launch_wide_mode(const P1Args& a, int KL, hipStream_t s) {
-  if (KL <= 2) return launch_wide_one<MODE, 2, PREC, LONG, SM>(a, s);
-  if (KL <= 4) return launch_wide_one<MODE, 4, PREC, LONG, SM>(a, s);
-  if (KL <= 8) return launch_wide_one<MODE, 8, PREC, LONG, SM>(a, s);
-  if (KL <= 16) return launch_wide_one<MODE, 16, PREC, LONG, SM>(a, s);
-  if (KL <= 32) return launch_wide_one<MODE, 32, PREC, LONG, SM>(a, s);
+  if (KL <= 2) return launch_wide_one<MODE, 2, PREC, LONG>(a, s);
+  if (KL <= 4) return launch_wide_one<MODE, 4, PREC, LONG>(a, s);
+  if (KL <= 8) return launch_wide_one<MODE, 8, PREC, LONG>(a, s);
+  if (KL <= 16) return launch_wide_one<MODE, 16, PREC, LONG>(a, s);
+  if (KL <= 32) return launch_wide_one<MODE, 32, PREC, LONG>(a, s);
   return hipErrorInvalidValue;
 }
 
-template <int PREC, bool LONG = false, bool SM = false>
+template <int PREC, bool LONG = false>
 static hipError_t launch_wide_prec(const P1Args& a, int mode, int KL, hipStream_t s) {
   switch (mode) {
-    case P1_TABLE: return launch_wide_mode<P1_TABLE, PREC, LONG, SM>(a, KL, s);
-    case P1_TABLE_FULL: return launch_wide_mode<P1_TABLE_FULL, PREC, LONG, SM>(a, KL, s);
-    case P1_PAIR: return launch_wide_mode<P1_PAIR, PREC, LONG, SM>(a, KL, s);
+    case P1_TABLE: return launch_wide_mode<P1_TABLE, PREC, LONG>(a, KL, s);
+    case P1_TABLE_FULL: return launch_wide_mode<P1_TABLE_FULL, PREC, LONG>(a, KL, s);
+    case P1_PAIR: return launch_wide_mode<P1_PAIR, PREC, LONG>(a, KL, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1042,14 +980,8 @@ int phase1_wide_rows() { return kWR; }
 
 hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, int seg_hmax, hipStream_t s) {
   if (seg_hmax > kSegLong) return hipErrorInvalidValue;
-  // float32 with at most 28 dims: the one-short-slice kernels
-  const bool sm = prec == PREC_F32 && a.m4 >= 1 && a.m4 <= 7;
-  if (seg_hmax > kSeg) {
-    if (prec != PREC_F32) return hipErrorInvalidValue;
-    return sm ? launch_wide_prec<PREC_F32, true, true>(a, mode, KL, s) : launch_wide_prec<PREC_F32, true>(a, mode, KL, s);
-  }
-  if (prec == PREC_F32)
-    return sm ? launch_wide_prec<PREC_F32, false, true>(a, mode, KL, s) : launch_wide_prec<PREC_F32>(a, mode, KL, s);
+  if (seg_hmax > kSeg) return prec == PREC_F32 ? launch_wide_prec<PREC_F32, true>(a, mode, KL, s) : hipErrorInvalidValue;
+  if (prec == PREC_F32) return launch_wide_prec<PREC_F32>(a, mode, KL, s);
   if (prec == PREC_BF16) {
     if (!a.Vb) return hipErrorInvalidValue;
     return launch_wide_prec<PREC_BF16>(a, mode, KL, s);
