@@ -113,12 +113,14 @@ def test_k_beyond_histogram_length_is_ict(L):
         P.assert_distances(g, ict.astype(np.float64), f"k={k}")
 
 
-def test_maximum_length_queries(L):
+@pytest.mark.parametrize("m", [8, 40])
+def test_maximum_length_queries(L, m):
     """Queries of LCEMD_MAX_HIST words (every word of a 1,024-word
-    vocabulary) against short and long database rows."""
+    vocabulary) against short and long database rows; m = 8 runs the 64-row
+    phase-1 kernel, m = 40 the long-segment variant of the 128-row one."""
     rng = np.random.default_rng(25)
     v = L.MAX_HIST
-    V = rng.standard_normal((v, 8)).astype(np.float32)
+    V = rng.standard_normal((v, m)).astype(np.float32)
     cols = [np.sort(rng.choice(v, h, replace=False)) for h in (1, 40, 700, 1024)]
     rows = [(c, rng.random(c.size) + 0.05) for c in cols]
     db = _csr(rows)
@@ -126,7 +128,7 @@ def test_maximum_length_queries(L):
     ctx = L.open_context(V, db.rowptr, db.col, db.val)
     orc = O.Oracle(V, db.rowptr, db.col, db.val)
     for method, k in (("rwmd", 1), ("act", 4), ("ict", 1)):
-        say(f"[gpu] 1024-word queries {method} k={k}")
+        say(f"[gpu] 1024-word queries m={m} {method} k={k}")
         o = orc.matrix(q.rowptr, q.col, q.val, method, k, "sym")
         P.assert_distances(ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="sym"), o,
                            f"max length {method}")
