@@ -65,7 +65,7 @@ def phase1_kernel(method, k, precision, m):
     while kl < depth + margin:
         kl *= 2
     prec = 0 if margin == 0 else 1
-    if prec == 0 and (m + 3) // 4 <= 7 and depth <= 64:  # float32, at most 28 dims: 64-row kernel
+    if prec == 0 and (m + 3) // 4 <= 7 and depth <= 64 and method != "ict":  # float32, at most 28 dims: 64-row kernel
         return f"k_phase1_fast<0, {kl}, 0>"
     if depth + margin <= 32:
         return f"k_phase1_wide<0, {kl}, {prec}, false>"

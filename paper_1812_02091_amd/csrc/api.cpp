@@ -281,8 +281,11 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
   a.m8 = c->m8;
   // float32 with at most 28 dims (image coordinates): the 64-row kernel,
   // whose row blocks waste less of ~160-word histograms and whose exact keys
-  // need no redo of rows with tied grid distances
-  const bool small_m = prec == LCEMD_FP32 && a.m4 <= 7;
+  // need no redo of rows with tied grid distances.  Not for ICT tables: the
+  // 128-row kernel redoes rows deeper than their list one by one, where the
+  // 64-row kernel can only report overflow (and the tables are rebuilt at
+  // full depth)
+  const bool small_m = prec == LCEMD_FP32 && a.m4 <= 7 && !(mode == P1_TABLE && a.method == LCEMD_ICT);
   if (depth + margin <= 32 && !c->force_kernel && !small_m) {
     const int KL = pow2ceil(depth + margin);
     a.KT_margin = margin;
