@@ -258,12 +258,11 @@ int ensure_precision(lcemd_ctx* c, int prec) {
 
 // Launch phase 1: rows of `a` may need up to `depth` list entries.  Lists of
 // up to 32 entries (with the bf16 margin) run on the 128-row kernel, up to
-// 64 (and the pair mode, and float32 embeddings of at most 28 dims, at any
-// depth up to 64) on the 64-row streaming kernel, deeper rows on the kernel
-// that keeps a whole row of keys in LDS (float32 keys).  Pair mode: a.rb_max
-// is set to the row-block count of the chosen kernel for queries of up to
-// row_hmax words (callers size `partial` for 64-row blocks, the largest
-// count).
+// 64 (and float32 embeddings of at most 28 dims at any depth up to 64) on
+// the 64-row streaming kernel, deeper rows on the kernel that keeps a
+// whole row of keys in LDS (float32 keys).  Pair mode: a.rb_max is set to
+// the row-block count of the chosen kernel for queries of up to row_hmax
+// words (callers size `partial` for 64-row blocks, the largest count).
 int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hmax,
               int row_hmax) {
   // bf16 keys carry an exactness certificate only on the 128-row kernel;
@@ -280,16 +279,14 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
   a.V8 = c->V8;
   a.vscale = c->vscale;
   a.m8 = c->m8;
-  // The 64-row kernel also takes (a) the pair mode, whose 64-bit keys it
-  // handles with smaller row blocks, and (b) float32 with at most 28 dims
-  // (image coordinates), whose row blocks waste less of ~160-word histograms
-  // and whose exact keys need no redo of rows with tied grid distances --
-  // except ICT tables: the 128-row kernel redoes rows deeper than their list
-  // one by one, where the 64-row kernel can only report overflow (and the
-  // tables are rebuilt at full depth)
-  const bool rows64 = prec == LCEMD_FP32 &&
-                      (mode == P1_PAIR || (a.m4 <= 7 && !(mode == P1_TABLE && a.method == LCEMD_ICT)));
-  if (depth + margin <= 32 && !c->force_kernel && !rows64) {
+  // float32 with at most 28 dims (image coordinates): the 64-row kernel,
+  // whose row blocks waste less of ~160-word histograms and whose exact keys
+  // need no redo of rows with tied grid distances.  Not for ICT tables: the
+  // 128-row kernel redoes rows deeper than their list one by one, where the
+  // 64-row kernel can only report overflow (and the tables are rebuilt at
+  // full depth)
+  const bool small_m = prec == LCEMD_FP32 && a.m4 <= 7 && !(mode == P1_TABLE && a.method == LCEMD_ICT);
+  if (depth + margin <= 32 && !c->force_kernel && !small_m) {
     const int KL = pow2ceil(depth + margin);
     a.KT_margin = margin;
     a.rb_max = (row_hmax + phase1_wide_rows() - 1) / phase1_wide_rows();
