@@ -192,3 +192,25 @@ def test_unknown_load_flags_rejected(L):
     assert rc == L.E_INVALID_ARG
     after = ctx.distances(db.rowptr, db.col, db.val, method="act", k=2, direction="sym")
     assert np.array_equal(before, after)
+
+
+def test_batch_lanes_with_unaligned_rows_and_short_tail(L):
+    """More than 32 queries (64 query lanes, results staged and stored 16 at
+    a time) against 150 documents: output rows of odd queries start off a
+    16-byte boundary and the last item of each row holds 6 documents.  The
+    distances equal the oracle's, and bit for bit those of 5-query batches
+    (8 query lanes, stored one by one)."""
+    from synth import make_workload
+
+    w = make_workload("tiny", n=150, B=40)
+    ctx = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val)
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    q = w.queries
+    for method, k in (("rwmd", 1), ("act", 3)):
+        say(f"[gpu] 40 queries x 150 documents {method} k={k} d2q")
+        g = ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="d2q")
+        P.assert_distances(g, orc.matrix(q.rowptr, q.col, q.val, method, k, "d2q"), f"{method} d2q")
+        for b0 in range(0, 40, 5):
+            s = q.take(list(range(b0, b0 + 5)))
+            part = ctx.distances(s.rowptr, s.col, s.val, method=method, k=k, direction="d2q")
+            assert np.array_equal(part, g[b0:b0 + 5]), (method, b0)
