@@ -113,3 +113,18 @@ def test_validation_row_sum_optional_and_capacity():
 def test_opts_layout_matches_header():
     assert ctypes.sizeof(L.lcemd_opts) == 8 * 4
     assert ctypes.sizeof(L.lcemd_query) == 8 * 3 + 8 + 8
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and
+    says why, before touching a device."""
+    import json
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2, r.stderr[-2000:]
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    assert rec["n_gpus"] == 2 and "one GPU" in rec["error"]
