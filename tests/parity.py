@@ -69,16 +69,46 @@ def check_table_rows(S_gpu, Z_gpu, W_gpu, S_or, R_or, qw, k, hq):
     return diff_rows, S_or.shape[0]
 
 
-def check_topl(idx_gpu, dist_gpu, oracle_row, ell, what=""):
-    """GPU top-l list against the oracle's full distance row."""
+def check_topl(idx_gpu, dist_gpu, oracle_row, ell, what="", tol_row=None):
+    """GPU top-l list against the oracle's full distance row (entries the
+    caller wants excluded set to +inf).  Returns the number of list
+    positions whose index differs from the oracle's (distance, index)
+    order; callers cap it.
+
+    Whatever the tie order, the list must be a valid top-l:
+    * l distinct in-range rows, ascending by (GPU distance, index);
+    * each returned distance equal to the oracle's for that row within
+      tolerance;
+    * no returned row beyond the oracle's l-th distance by more than the
+      tolerance of both, and no row left out that is nearer than the
+      farthest returned one by more than the tolerance of both -- so a list
+      that drops a clearly nearer row fails even when the next row ties
+      with the l-th.
+    tol_row: per-row distance tolerance (default: dist_tol of the row)."""
     o = np.asarray(oracle_row, dtype=np.float64)
     order = np.lexsort((np.arange(o.size), o))[:ell]
     ig = np.asarray(idx_gpu, dtype=np.int64)
+    dg = np.asarray(dist_gpu, dtype=np.float64)
+    assert ig.shape == (ell,) and dg.shape == (ell,), (what, ig.shape, dg.shape)
     assert len(set(ig.tolist())) == ell and ig.min() >= 0 and ig.max() < o.size, what
-    tol = dist_tol(o)
-    assert np.all(np.abs(np.asarray(dist_gpu, dtype=np.float64) - o[ig]) <= tol[ig]), what
-    if np.array_equal(ig, order):
+    assert np.all(np.isfinite(o[ig])), (what, "returned an excluded row")
+    # ascending by (distance, index) in the returned values themselves
+    for j in range(ell - 1):
+        assert (dg[j], ig[j]) < (dg[j + 1], ig[j + 1]), (what, "list not ascending", j)
+    fin = np.isfinite(o)
+    tol = np.full(o.shape, np.inf)
+    tol[fin] = dist_tol(o[fin]) if tol_row is None else np.asarray(tol_row, dtype=np.float64)[fin]
+    bad = np.abs(dg - o[ig]) > tol[ig]
+    assert not bad.any(), (what, "distance off", ig[bad][:4], dg[bad][:4], o[ig][bad][:4])
+    swaps = int(np.sum(ig != order))
+    if swaps == 0:
         return 0
-    kth = o[order[-1]]
-    assert np.all(o[ig] <= kth + tol[order[-1]] * 2), (what, "returned a row beyond the l-th")
-    return 1
+    kth = order[-1]
+    assert np.all(o[ig] <= o[kth] + tol[ig] + tol[kth]), (what, "returned a row beyond the l-th")
+    far = ig[np.argmax(o[ig])]
+    left = np.ones(o.size, dtype=bool)
+    left[ig] = False
+    left &= fin
+    nearer = left & (o < o[far] - tol - tol[far])
+    assert not nearer.any(), (what, "left out a nearer row", np.nonzero(nearer)[0][:4], o[far])
+    return swaps

@@ -86,6 +86,28 @@ def test_tables_tiny(tiny, k):
     assert diff <= 2
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("k", [4, 16])
+def test_tables_text_default_kernel(text_small, k, prec):
+    """Phase-1 tables at the text shape (m = 300, 50-300-word queries, several
+    64-column passes and a ragged last row block) on the kernel the library
+    picks by default for that precision: index sets equal the oracle's
+    tie-broken sets except inside the float32 tie band, Z and W per entry."""
+    w, ctx, orc = text_small
+    say(f"[gpu] tables text m=300 k={k} {prec}")
+    S, Z, W = ctx.tables(*_q(w), k=k, precision=prec)
+    assert np.array_equal(ctx.used_vocab(), orc.used)
+    diff = rows = 0
+    for b in range(w.queries.n):
+        qc, qw = w.queries.row(b)
+        So, Zo, Wo, R = orc.tables(qc, qw, k)
+        d, r = P.check_table_rows(S[b], Z[b], W[b], So, R, qw, k, qc.size)
+        diff += d
+        rows += r
+    say(f"  rows differing inside the float32 tie band: {diff} of {rows}")
+    assert diff <= 2
+
+
 @pytest.mark.parametrize("k", [1, 4, 16])
 def test_tables_image_exact_ties(image_small, k):
     """Integer grid: squared distances are exact in float32, so the index
@@ -191,7 +213,7 @@ def test_topl_tiny(tiny, method, k, direction):
     idx, dist = ctx.topl(*_q(w), 5, method=method, k=k, direction=direction)
     o = _oracle_matrix(orc, w, method, k, direction)
     swaps = sum(P.check_topl(idx[b], dist[b], o[b], 5, f"b={b}") for b in range(w.queries.n))
-    assert swaps <= 1
+    assert swaps <= 2, swaps  # at most one pair of neighbours tied within tolerance
 
 
 @pytest.mark.parametrize("ell", [1, 16, 150])
@@ -200,8 +222,8 @@ def test_topl_text_sym(text_small, ell):
     say(f"[gpu] top-{ell} text act8 sym")
     idx, dist = ctx.topl(*_q(w), ell, method="act", k=8, direction="sym")
     o = _oracle_matrix(orc, w, "act", 8, "sym")
-    for b in range(w.queries.n):
-        P.check_topl(idx[b], dist[b], o[b], ell, f"b={b}")
+    swaps = sum(P.check_topl(idx[b], dist[b], o[b], ell, f"b={b}") for b in range(w.queries.n))
+    assert swaps <= 2, swaps
 
 
 def test_topl_exclude_self(L):
@@ -214,9 +236,11 @@ def test_topl_exclude_self(L):
         assert 10 + b not in idx[b].tolist()
     orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
     o = orc.matrix(q.rowptr, q.col, q.val, "act", 2, "sym")
+    swaps = 0
     for b in range(6):
         o[b, 10 + b] = np.inf
-        P.check_topl(idx[b], dist[b], o[b], 4)
+        swaps += P.check_topl(idx[b], dist[b], o[b], 4, f"b={b}")
+    assert swaps <= 2, swaps
 
 
 def test_device_pointer_path_matches_host(tiny):
@@ -293,8 +317,8 @@ def test_topl_bf16_text(text_small):
     say("[gpu] bf16 top-16 text act8 sym")
     idx, dist = ctx.topl(*_q(w), 16, method="act", k=8, direction="sym", precision="bf16")
     o = _oracle_matrix(orc, w, "act", 8, "sym")
-    for b in range(w.queries.n):
-        P.check_topl(idx[b], dist[b], o[b], 16, f"b={b}")
+    swaps = sum(P.check_topl(idx[b], dist[b], o[b], 16, f"b={b}") for b in range(w.queries.n))
+    assert swaps <= 2, swaps
 
 
 @pytest.mark.parametrize("force", ["1", "2"])
@@ -332,6 +356,7 @@ def test_topl_many_documents(L, direction, ell):
     idx, dist = ctx.topl(*_q(w), ell, method="act", k=4, direction=direction, exclude_self=excl)
     full = ctx.distances(*_q(w), method="act", k=4, direction=direction)
     orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    swaps = 0
     for b in range(w.queries.n):
         row = full[b].astype(np.float64).copy()
         row[excl + b] = np.inf
@@ -340,11 +365,12 @@ def test_topl_many_documents(L, direction, ell):
             assert np.array_equal(idx[b], order), b
             assert np.array_equal(dist[b], full[b][order]), b
         else:
-            P.check_topl(idx[b], dist[b], row, ell, f"query {b}")
+            swaps += P.check_topl(idx[b], dist[b], row, ell, f"query {b}")
         qc, qw = w.queries.row(b)
         for j in range(0, ell, max(1, ell // 8)):
             o = orc.pair(qc, qw, int(idx[b, j]), "act", 4, direction)
             assert abs(float(dist[b, j]) - o) <= 1e-5 * abs(o) + 1e-7, (b, j)
+    assert swaps <= 4, swaps  # the two reverse computations round differently
 
 
 @pytest.mark.parametrize("wl", ["tiny", "text"])

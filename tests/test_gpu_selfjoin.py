@@ -61,7 +61,7 @@ def test_selfjoin_matches_oracle(L, tiny, method, k, direction):
     idx, dist = ctx.selfjoin_topl(5, method=method, k=k, direction=direction)
     M = _masked(orc.matrix(w.db.rowptr, w.db.col, w.db.val, method, k, direction))
     swaps = _check_against_rows(idx, dist, M, 5, f"{method} {direction}")
-    assert swaps <= 3, swaps
+    assert swaps <= 6, swaps  # list positions: at most three adjacent pairs tied within tolerance
 
 
 def test_selfjoin_equals_topl_on_database_rows(L, tiny):
@@ -113,11 +113,13 @@ def test_selfjoin_image_rows(L):
     hi, hd = ctx.selfjoin_topl(16, method="act", k=2, direction="sym")
     assert np.array_equal(idx, hi) and np.array_equal(dist, hd)
     orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    swaps = 0
     for b in (7, 1234):
         c, v = w.db.row(b)
         row = np.asarray(orc.row_distances(c, v, "act", 2, "sym"), dtype=np.float64)
         row[b] = np.inf
-        P.check_topl(idx[b], dist[b], row, 16, f"image row {b}")
+        swaps += P.check_topl(idx[b], dist[b], row, 16, f"image row {b}")
+    assert swaps <= 2, swaps
     assert np.all(np.diff(dist, axis=1) >= 0)
 
 

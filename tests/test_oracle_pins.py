@@ -377,3 +377,58 @@ def test_dense_background_images_closed_forms():
             act4 = orc.row_distances(c, qv, "act", 4, d)
             ict = orc.row_distances(c, qv, "ict", 1, d)
             assert np.all(tv > 0) and np.all(act2 <= act4 + 1e-12) and np.all(act4 <= ict + 1e-12)
+
+
+# --------------------------------------------------------------------------
+# top-l order, the bulk RWMD bound, OMR with repeated coordinates
+# --------------------------------------------------------------------------
+def test_top_l_ties_go_to_lower_index():
+    """Sec. 5 top-l: ascending distance, equal distances by ascending
+    document index -- checked on a worked row and against brute force
+    (Python's tuple sort) on integer rows full of ties."""
+    row = np.array([3.0, 1.0, 2.0, 1.0, 0.0, 2.0, 1.0])
+    idx, dist = O.Oracle.top_l(row, 4)
+    assert idx.tolist() == [4, 1, 3, 6] and dist.tolist() == [0.0, 1.0, 1.0, 1.0]
+    rng = np.random.default_rng(41)
+    for _ in range(200):
+        n = int(rng.integers(1, 40))
+        r = rng.integers(0, 5, n).astype(np.float64)
+        ell = int(rng.integers(1, n + 1))
+        want = sorted(range(n), key=lambda i: (r[i], i))[:ell]
+        got, d = O.Oracle.top_l(r, ell)
+        assert got.tolist() == want and np.array_equal(d, r[want])
+
+
+def test_rwmd_bound_for_all_documents():
+    """The bulk one-sided RWMD equals the per-pair RWMD of every document
+    (Sec. 2.1 / Sec. 2.2) and lower-bounds ACT and the symmetric measure
+    (Thm 2, and SYM >= D2Q)."""
+    w = make_workload("tiny", n=60, B=3)
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    for b in range(w.queries.n):
+        qc, qw = w.queries.row(b)
+        bulk = orc.rwmd_d2q_all(qc)
+        pairs = orc.row_distances(qc, qw, "rwmd", 1, "d2q")
+        assert np.allclose(bulk, pairs, rtol=1e-12, atol=0)
+        for method, k, d in (("act", 4, "d2q"), ("ict", 1, "d2q"), ("act", 2, "sym")):
+            assert np.all(bulk <= orc.row_distances(qc, qw, method, k, d) * (1 + 1e-12))
+
+
+def test_omr_with_repeated_coordinates_follows_sec_3_1():
+    """A destination coordinate that occurs twice (not a valid histogram,
+    but the grid instances above make them): the nearest overlapping
+    destination is capped and the rest goes to the second closest, which
+    here overlaps too -- so OMR stays at ACT(2) (Thm 2's order holds), below
+    the program that caps every zero-cost pair.  Distinct coordinates: OMR
+    is that program's optimum (test_rwmd_and_omr_lps)."""
+    C = _c1d([0.0], [0.0, 0.0, 2.0])
+    p, q = np.array([1.0]), np.array([0.3, 0.3, 0.4])
+    assert O.omr(p, q, C) == 0.0 and O.act(p, q, C, 2) == 0.0
+    assert abs(O.relaxed_lp(p, q, C, C == 0) - 0.8) < 1e-9
+    assert abs(O.ict(p, q, C) - 0.8) < 1e-12
+    # overlap with a second, distinct destination: 0.3 free, 0.7 at cost 2
+    C2 = _c1d([0.0], [0.0, 2.0])
+    assert abs(O.omr(p, np.array([0.3, 0.7]), C2) - 1.4) < 1e-12
+    # one destination only, at the same coordinate: nothing to pay (the last
+    # destination absorbs the rest)
+    assert O.omr(np.array([1.0]), np.array([1.0]), _c1d([0.0], [0.0])) == 0.0
