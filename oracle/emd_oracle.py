@@ -91,23 +91,20 @@ def rwmd(p, q, C, R=None) -> float:
 
 
 def omr(p, q, C, R=None) -> float:
-    """Overlapping Mass Reduction (Alg. 1).  Per source bin: if its nearest
-    destination is at cost exactly 0, move min(p_i, q_s1) there for free and
-    the rest to the second nearest; otherwise move all of p_i to the nearest."""
+    """Overlapping Mass Reduction (Sec. 3.1): the relaxed in-flow cap of
+    Eq. (4) is kept only between overlapping coordinates.  A source bin whose
+    nearest destination overlaps it (cost exactly 0) moves at most that
+    destination's weight there for free and the rest to its second closest
+    destination; every other bin moves all of its mass to its nearest
+    destination.  Row by row this is ACT with k = 2 where the nearest
+    destination overlaps and ACT with k = 1 elsewhere (Lemma 2's program
+    with the cap on that one pair), so it is computed from ``act_rows``."""
     p = np.asarray(p, dtype=np.float64)
-    q = np.asarray(q, dtype=np.float64)
     order = _order(C if R is None else R)
-    hq = C.shape[1]
-    t = 0.0
-    for i in range(C.shape[0]):
-        s1 = order[i, 0]
-        s2 = order[i, min(1, hq - 1)]
-        if C[i, s1] == 0.0:
-            rest = p[i] - min(p[i], q[s1])
-            t += rest * C[i, s2]
-        else:
-            t += p[i] * C[i, s1]
-    return float(t)
+    nearest = C[np.arange(C.shape[0]), order[:, 0]]
+    capped = act_rows(p, q, C, 2, R)
+    plain = act_rows(p, q, C, 1, R)
+    return float(np.sum(np.where(nearest == 0.0, capped, plain)))
 
 
 def act_rows(p, q, C, k: int, R=None) -> np.ndarray:
@@ -256,6 +253,22 @@ class Oracle:
         if direction == "q2d":
             return q2d
         return max(d2q, q2d)
+
+    def rwmd_d2q_all(self, qcols, R_block=None) -> np.ndarray:
+        """One-sided RWMD (Sec. 2.1) moving every database document into the
+        query, for all documents at once: each document word sends its whole
+        weight to its nearest query word.  Per document this is exactly
+        ``rwmd`` on its cost matrix; the nearest distance of a word is
+        shared by every document that holds it (Sec. 2.2)."""
+        if R_block is None:
+            R_block = self.query_block(qcols)
+        nearest = np.sqrt(R_block.min(axis=1))
+        contrib = self.val * nearest[self._pos[self.col]]
+        out = np.zeros(self.n)
+        lens = np.diff(self.ptr)
+        nz = lens > 0
+        out[nz] = np.add.reduceat(contrib, self.ptr[:-1][nz])
+        return out
 
     def row_distances(self, qcols, qw, method, k, direction, docs=None):
         """Distances from one query to the given documents (default: all)."""
