@@ -80,8 +80,9 @@ def test_text_full_size(L):
     for b in (int(bs[0]), int(bs[1])):  # whole rows: the top-16 itself
         qc, qw = w.queries.row(b)
         row = orc.row_distances(qc, qw, "act", 16, "sym")
-        P.check_topl(idx[b], dist[b], row, 16, f"query {b} fp32")
-        P.check_topl(ib[b], db[b], row, 16, f"query {b} bf16")
+        swaps = P.check_topl(idx[b], dist[b], row, 16, f"query {b} fp32")
+        swaps += P.check_topl(ib[b], db[b], row, 16, f"query {b} bf16")
+        assert swaps <= 2, (b, swaps)
     say("[gpu] full-size text done")
 
 
@@ -95,6 +96,13 @@ def test_image_full_size(L):
     orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
     bs, js = sample_pairs(3, w.queries.n, 16, 24)
     _check_pairs(orc, w, idx, dist, "act", 2, zip(bs, js))
+    swaps = 0
+    for b in (int(bs[0]), int(bs[1])):  # whole oracle rows: all 60,000 documents
+        say(f"[gpu] full-size image: oracle row of query {b}")
+        qc, qw = w.queries.row(b)
+        row = orc.row_distances(qc, qw, "act", 2, "sym")
+        swaps += P.check_topl(idx[b], dist[b], row, 16, f"query {b}")
+    assert swaps <= 2, swaps
     say("[gpu] full-size image done")
 
 
@@ -124,3 +132,48 @@ def test_text_1m_vocabulary(L):
         o = orc.pair(qc, qw, pos[int(idx[b, j])], "act", 8, "sym")
         P.assert_distances(np.array([dist[b, j]]), np.array([o]), f"query {b} rank {j}")
     say("[gpu] 1M-word workload done")
+
+
+def certified_row(orc, qc, qw, method, k, tau, tol_frac=1e-5):
+    """The oracle's symmetric distances of one query against the whole
+    database wherever they can reach the top-l: every document whose
+    one-sided RWMD (moving the document into the query) is at most tau plus
+    tolerance is evaluated exactly; every other document is provably farther
+    (SYM >= D2Q >= RWMD, Thm 2) and keeps its bound.  Returns (row, exact):
+    the row and a mask of the exactly evaluated documents."""
+    R = orc.query_block(qc)
+    bound = orc.rwmd_d2q_all(qc, R)
+    exact = bound <= tau * (1 + 4 * tol_frac) + 1e-6
+    row = bound.copy()
+    for u in np.nonzero(exact)[0]:
+        row[u] = orc.pair(qc, qw, int(u), method, k, "sym", R)
+    return row, exact
+
+
+def test_text_1m_whole_rows(L):
+    """1M-word vocabulary, 1M documents, ACT k=8 symmetric top-16 (the
+    precision workload's shape): for two queries the float32 and bf16 lists
+    against whole oracle rows, certified by RWMD lower bounds -- the oracle
+    evaluates exactly every document that could enter the top-16, and no
+    other document can."""
+    import torch
+
+    w = make_workload("text-1M", B=16)
+    say("[gpu] 1M-word workload, 16 queries, whole-row certificate")
+    ctx, idx, dist = _device_topl(L, w, 16, method="act", k=8, direction="sym", precision="fp32")
+    dev = torch.device("cuda:0")
+    q = [torch.from_numpy(x).to(dev) for x in (w.queries.rowptr, w.queries.col, w.queries.val)]
+    ib, db = ctx.topl(*q, 16, method="act", k=8, direction="sym", precision="bf16")
+    ib, db = ib.cpu().numpy(), db.cpu().numpy()
+    ctx.close()
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    swaps = 0
+    for b in (3, 11):
+        qc, qw = w.queries.row(b)
+        tau = float(max(dist[b, -1], db[b, -1]))
+        row, exact = certified_row(orc, qc, qw, "act", 8, tau)
+        say(f"  query {b} ({qc.size} words): {int(exact.sum())} documents evaluated exactly")
+        assert exact[idx[b]].all() and exact[ib[b]].all()
+        swaps += P.check_topl(idx[b], dist[b], row, 16, f"query {b} fp32")
+        swaps += P.check_topl(ib[b], db[b], row, 16, f"query {b} bf16")
+    assert swaps <= 2, swaps

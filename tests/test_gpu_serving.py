@@ -9,7 +9,9 @@ import threading
 import numpy as np
 import pytest
 
+from oracle import emd_oracle as O
 from synth import arrival_trace, make_workload
+import parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -121,3 +123,29 @@ def test_server_memory_budget_too_small(setup):
     with pytest.raises(L.LcemdError) as e:
         L.Server(ctx, method="act", k=8, l=8, memory_budget=1024)
     assert e.value.code == L.E_CAPACITY
+
+
+@pytest.mark.parametrize("prec,graph", [("bf16", True), ("fp32", False)])
+def test_server_matches_oracle(setup, prec, graph):
+    """Serving results against whole float64 oracle rows (Sec. 5 top-l,
+    ACT k=8 symmetric, m = 300): ten queries of the arrival trace, the
+    longest ones (300-500 words) among them, submitted together so that
+    they share batches."""
+    L, w, qs, ctx = setup
+    lens = np.diff(qs.rowptr)
+    picks = sorted(set(np.argsort(lens)[-5:].tolist()) | {0, 1, 2, 3, 4})
+    assert lens[picks].max() >= 300
+    say(f"[gpu] server vs oracle {prec} graph={graph}: queries of {sorted(lens[picks].tolist())} words")
+    orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
+    srv = L.Server(ctx, method="act", k=8, precision=prec, l=16, max_slots=8, use_graph=graph)
+    try:
+        tickets = [srv.submit(*qs.row(b)) for b in picks]
+        got = [srv.wait(t) for t in tickets]
+    finally:
+        srv.stop()
+    swaps = 0
+    for b, (i, d, _) in zip(picks, got):
+        qc, qw = qs.row(b)
+        row = orc.row_distances(qc, qw, "act", 8, "sym")
+        swaps += P.check_topl(i, d, row, 16, f"query {b} ({qc.size} words)")
+    assert swaps <= 2, swaps
