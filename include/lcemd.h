@@ -245,8 +245,8 @@ int lcemd_profile_get(lcemd_ctx* ctx, lcemd_phase_time* out, int cap);
 
 /* ---------------------------------------------------------------------
  * Serving: continuous batching of a query stream against the resident
- * database, returning each query's symmetric top-l (Sec. 5, Eq. 10 with the
- * exact pruning of lcemd_topl).  Submitted queries wait in a FIFO; a worker
+ * database, returning each query's symmetric top-l (the top-l search of
+ * Sec. 5, with the exact pruning of lcemd_topl).  Submitted queries wait in a FIFO; a worker
  * thread admits them into a free lane (a stream with preallocated device
  * and pinned host buffers for up to B queries and W words), runs the lane's
  * whole batch -- phase 1 tables, the exact redo of uncertified rows, phase 2 on a persistent kernel fed by per-XCD work counters, D2Q
@@ -284,7 +284,7 @@ typedef struct {
  * LCEMD_SERVE_MAX_HIST words.  *out is NULL on error. */
 int lcemd_server_start(lcemd_ctx* ctx, const lcemd_server_cfg* cfg, lcemd_server** out);
 /* Queue one query (host arrays of h words: ascending distinct ids < v,
- * weights >= 0 summing to 1; copied before return).  *ticket gets its id.
+ * finite weights > 0 summing to 1 within 1e-5; copied before return).  *ticket gets its id.
  * LCEMD_E_BAD_CSR for a malformed query, LCEMD_E_CAPACITY for h >
  * LCEMD_SERVE_MAX_HIST.  Thread-safe. */
 int lcemd_server_submit(lcemd_server* s, const int32_t* col, const float* val, int32_t h,

@@ -1042,13 +1042,25 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
     HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&h_fix, fixc, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (h_ovf) {  // redo everything with float32 keys
+    if (h_ovf) {
+      // redo everything with float32 keys: rows listed for an exact redo by
+      // the first launch are dropped (the rerun lists its own), and an
+      // overflow of the rerun itself is an error
       HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
+      HIPCHK(c, hipMemsetAsync(fixc, 0, sizeof(int), c->stream));
       if ((rc = p1_launch(c, a, P1_TABLE_FULL, LCEMD_FP32, o->k, Q.hmax, Q.hmax))) return rc;
       ++c->fallbacks;
-    } else if (h_fix > 0) {
+      HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(&h_fix, fixc, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (h_ovf) return fail(c, LCEMD_E_CAPACITY, "tables: rows need more candidates than the kernels keep");
+    }
+    if (h_fix > 0) {
       HIPCHK(c, launch_fix_rows(a, P1_TABLE_FULL, h_fix, c->stream));
       c->fixed_rows += h_fix;
+      HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (h_ovf) return fail(c, LCEMD_E_CAPACITY, "tables: rows need more candidates than the kernels keep");
     }
   }
   if (!Q.device) {
