@@ -246,13 +246,20 @@ int lcemd_profile_get(lcemd_ctx* ctx, lcemd_phase_time* out, int cap);
 /* ---------------------------------------------------------------------
  * Serving: continuous batching of a query stream against the resident
  * database, returning each query's symmetric top-l (the top-l search of
- * Sec. 5, with the exact pruning of lcemd_topl).  Submitted queries wait in a FIFO; a worker
- * thread admits them into a free lane (a stream with preallocated device
- * and pinned host buffers for up to B queries and W words), runs the lane's
- * whole batch -- phase 1 tables, the exact redo of uncertified rows, phase 2 on a persistent kernel fed by per-XCD work counters, D2Q
- * candidate selection, Q2D of the candidates, symmetric top-l -- and
- * completes each query independently.  A query whose top-l certificate
- * fails, or whose lists overflowed, is finished by lcemd_topl.
+ * Sec. 5, with the exact pruning of lcemd_topl).  The device memory budget
+ * is split at start into `lanes` launch lanes, each a stream with
+ * preallocated device and pinned host buffers for up to B queries and W
+ * words.  Submitted queries wait in one FIFO; whenever a lane is free and
+ * queries wait, the lane takes the FIFO head's queries (as many as fit its
+ * B slots and W words) and launches at once -- no batch waits to fill, and
+ * queries that arrive while other batches run join the next free lane, so
+ * up to `lanes` batches overlap on the device.  A batch runs phase 1
+ * tables, the exact redo of uncertified rows, phase 2 on a persistent
+ * kernel fed by per-XCD work counters, D2Q candidate selection, Q2D of the
+ * candidates and the symmetric top-l, and completes each query
+ * independently.  A query whose top-l certificate fails, or whose lists
+ * overflowed, is finished by lcemd_topl.  lcemd_serve_sim runs the same
+ * admission policy on the host against a fake executor.
  *
  * Results depend only on the query, never on the others sharing a batch.
  * For RWMD, OMR and ACT (k <= the query's word count) they are also the
@@ -273,15 +280,17 @@ typedef struct {
   int32_t max_slots;       /* queries per batch (>= 1); lowered to fit memory_budget */
   int32_t max_batch_words; /* words per batch (raised to LCEMD_SERVE_MAX_HIST); 0 = no limit */
   int64_t memory_budget;   /* device bytes for all lanes' buffers; 0 = 4 GiB */
-  int32_t use_graph;       /* nonzero: two lanes, each batch replayed as a captured hipGraph
-                              (while one runs, the other starts once max_slots/2 queries
-                              wait); zero: one lane, kernels launched per batch */
-  int32_t reserved[5];     /* must be 0 */
+  int32_t use_graph;       /* nonzero: each lane's batch replayed as a captured hipGraph;
+                              zero: kernels launched per batch */
+  int32_t lanes;           /* batches in flight, 0..16; 0 = 4 with use_graph, 1 without */
+  int32_t reserved[4];     /* must be 0 */
 } lcemd_server_cfg;
 
-/* Allocates every lane buffer up front.  LCEMD_E_CAPACITY if the budget
- * holds no query or a database histogram has more than
- * LCEMD_SERVE_MAX_HIST words.  *out is NULL on error. */
+/* Allocates every lane buffer up front: B = the slots per lane that the
+ * budget allows (lanes x B x per-query bytes within memory_budget), at most
+ * max_slots.  LCEMD_E_CAPACITY if the budget holds no query or a database
+ * histogram has more than LCEMD_SERVE_MAX_HIST words.  *out is NULL on
+ * error. */
 int lcemd_server_start(lcemd_ctx* ctx, const lcemd_server_cfg* cfg, lcemd_server** out);
 /* Queue one query (host arrays of h words: ascending distinct ids < v,
  * finite weights > 0 summing to 1 within 1e-5; copied before return).  *ticket gets its id.
@@ -298,6 +307,22 @@ int lcemd_server_wait(lcemd_server* s, uint64_t ticket, int64_t* idx, float* dis
 /* Finish every queued query, stop the worker and free the server (results
  * not yet waited for are dropped).  NULL-safe. */
 void lcemd_server_stop(lcemd_server* s);
+
+/* The serving admission policy run on the host (no GPU) against a fake
+ * executor on a virtual clock, for testing it: nq queries arriving at
+ * arrival_s[i] (non-decreasing) with words[i] words; `lanes` lanes whose
+ * slots per lane are planned from budget and per_query_bytes like the
+ * server's (at most max_slots), max_words words per lane; a launch of q
+ * queries lasts t_fixed_s + t_per_query_s * q.  Per query: status
+ * (LCEMD_OK, or LCEMD_E_CAPACITY when it has more than max_words words and
+ * is refused), lane and launch index (-1 if refused), start and finish time.
+ * Returns the slots per lane (> 0), LCEMD_E_CAPACITY if the budget holds
+ * no query, LCEMD_E_INVALID_ARG for bad arguments.  All arrays are host
+ * memory of nq entries, caller-owned. */
+int lcemd_serve_sim(int32_t nq, const double* arrival_s, const int32_t* words, int32_t lanes,
+                    int32_t max_slots, int32_t max_words, int64_t budget, double per_query_bytes,
+                    double t_fixed_s, double t_per_query_s, int32_t* status, int32_t* lane,
+                    int32_t* launch, double* start_s, double* finish_s);
 
 #ifdef __cplusplus
 }

@@ -52,6 +52,9 @@ void free_emb(lcemd_ctx* c) {
   dfree((void*&)c->V);
   dfree((void*&)c->vnorm);
   dfree((void*&)c->Vb);
+  dfree((void*&)c->Vbq);
+  dfree((void*&)c->vres);
+  c->mb = 0;
   dfree((void*&)c->V8);
   dfree((void*&)c->vscale);
   c->v = 0;
@@ -239,9 +242,17 @@ int pow2ceil(int x) {
 
 int ensure_precision(lcemd_ctx* c, int prec) {
   if (prec == LCEMD_BF16 && !c->Vb) {
-    int rc = dalloc(c, c->Vb, (size_t)c->v * c->m_pad, "bfloat16 embeddings");
-    if (rc) return rc;
-    HIPCHK(c, launch_make_bf16(c->V, c->v * (int64_t)c->m_pad, c->Vb, c->stream));
+    const int mb = bf16_row_dims(c->m);
+    int rc = dalloc(c, c->Vb, (size_t)c->v * mb, "bfloat16 embeddings");
+    if (!rc) rc = dalloc(c, c->Vbq, (size_t)c->v * mb, "bfloat16 query-form embeddings");
+    if (!rc) rc = dalloc(c, c->vres, (size_t)c->v, "bfloat16 error norms");
+    if (rc) {
+      dfree((void*&)c->Vb);
+      dfree((void*&)c->Vbq);
+      return rc;
+    }
+    c->mb = mb;
+    HIPCHK(c, launch_make_bf16_rows(c->V, c->vnorm, c->v, c->m, c->m_pad, mb, c->Vb, c->Vbq, c->vres, c->stream));
   }
   if (prec == LCEMD_FP8 && !c->V8) {
     c->m8 = (c->m_pad + 127) / 128 * 128;
@@ -265,10 +276,12 @@ int ensure_precision(lcemd_ctx* c, int prec) {
 // words (callers size `partial` for 64-row blocks, the largest count).
 int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hmax,
               int row_hmax) {
-  // bf16 keys carry an exactness certificate only on the 128-row kernel;
-  // deeper lists use float32 keys
+  // reduced-precision keys carry their selection certificate on the table
+  // kernels for lists of up to 32 entries (bf16: its own kernel, rows of up
+  // to kBf16MaxDims dims); deeper lists and the pair mode use float32 keys
   if (prec != LCEMD_FP32 && (depth + kMargin > 32 || c->force_kernel || mode == P1_PAIR || seg_hmax > kSegShort))
     prec = LCEMD_FP32;
+  if (prec == LCEMD_BF16 && !(c->Vb && phase1_bf16_fits(c->mb, seg_hmax, depth))) prec = LCEMD_FP32;
   if (a.m4 < 1 || 4 * a.m4 > a.m_pad) return fail(c, LCEMD_E_INVALID_ARG, "internal: phase-1 arguments without their dims");
   if (!a.work_ctr) {
     int rc = wsget(c, "p1_counters", 8, a.work_ctr);
@@ -276,9 +289,29 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
   }
   const int margin = prec == LCEMD_FP32 ? 0 : kMargin;
   a.Vb = c->Vb;
+  a.Vbq = c->Vbq;
+  a.vres = c->vres;
+  a.mb = c->mb;
+  a.m = c->m;
   a.V8 = c->V8;
   a.vscale = c->vscale;
   a.m8 = c->m8;
+  if (prec == LCEMD_BF16) {
+    a.KT_margin = margin;
+    a.rb_max = 0;
+    // per-call row and query-word records (callers that capture graphs
+    // bring their own buffers; a.qnnz covers the batch's query non-zeros)
+    if (!a.rinfo) {
+      int rc = wsget(c, "bf16_rinfo", (size_t)a.v_used, a.rinfo);
+      if (rc) return rc;
+    }
+    if (!a.qinfo) {
+      int rc = wsget(c, "bf16_qinfo", (size_t)std::max<int64_t>(a.qnnz, 1), a.qinfo);
+      if (rc) return rc;
+    }
+    HIPCHK(c, launch_phase1_bf16(a, mode, depth, c->stream));
+    return LCEMD_OK;
+  }
   // float32 with at most 28 dims (image coordinates): the 64-row kernel,
   // whose row blocks waste less of ~160-word histograms and whose exact keys
   // need no redo of rows with tied grid distances.  Not for ICT tables: the
@@ -398,6 +431,7 @@ int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, 
     if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * db.v_used * 2 * zw_pairs(KT), ZW))) return rc;
     HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
     P1Args a = base_args(c, db, Q, o);
+    a.qnnz = Q.nnz;
     a.KT = KT;
     a.q0 = q0;
     a.nq = nq;
@@ -1018,6 +1052,7 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
   lcemd_opts oo = *o;
   oo.method = LCEMD_ACT;
   P1Args a = base_args(c, Q, &oo);
+  a.qnnz = Q.nnz;
   a.k = o->k;
   a.q0 = 0;
   a.nq = Q.B;

@@ -32,7 +32,10 @@ struct lcemd_ctx {
   int m = 0, m_pad = 0;
   float* V = nullptr;
   float* vnorm = nullptr;
-  uint16_t* Vb = nullptr;
+  uint16_t* Vb = nullptr;   // bfloat16 rows of mb dims (see P1Args::Vb)
+  uint16_t* Vbq = nullptr;  // their query form (see P1Args::Vbq)
+  float* vres = nullptr;    // |v - bf16(v)| per row
+  int mb = 0;
   uint8_t* V8 = nullptr;    // fp8 codes, rows of m8 bytes
   float* vscale = nullptr;  // fp8 row scales
   int m8 = 0;

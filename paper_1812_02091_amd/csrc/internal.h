@@ -27,6 +27,11 @@ constexpr int kSegShort = 512;
 // ICT's phase-1 lists stop here (its tables hold more); the few rows whose
 // capacities do not yet cover the word's largest weight are redone exactly.
 constexpr int kIctList = 16;
+// bfloat16 phase-1 rows: the real dims plus six folded-in terms, rounded up
+// to 64 dims; the bf16 kernel holds rows of up to this many dims in
+// registers (wider embeddings select with float32 keys).
+constexpr int kBf16MaxDims = 384;
+__host__ __device__ inline int bf16_row_dims(int m) { return (m + 6 + 63) / 64 * 64; }
 // The keys kernel for segments longer than kSegShort keeps its rows of keys
 // in device memory: one region of kRows x (LCEMD_MAX_HIST + 4) floats per
 // workgroup of a launch, launches of at most kDeepSlots workgroups.
@@ -49,7 +54,15 @@ struct P1Args {
   // embeddings
   const float* V;         // [v][m_pad] float32, zero padded
   const float* vnorm;     // [v] |v|^2 (float64 accumulation, stored float32)
-  const uint16_t* Vb;     // [v][m_pad] bfloat16 copy (PREC_BF16)
+  const uint16_t* Vb;     // [v][mb] bfloat16 rows: -2 v, then 1, 1, 1 and a three-piece
+                          // split of |v|^2 in the six dims after the m real ones
+  const uint16_t* Vbq;    // [v][mb] the same words as query operands: v, the split, 1, 1, 1
+  const float* vres;      // [v] |v - bf16(v)|, rounded up (bf16 error bound)
+  float4* rinfo;          // bf16 kernel scratch: [v_used] row records
+  float4* qinfo;          // bf16 kernel scratch: [qnnz] query-word records
+  int64_t qnnz;           // query non-zeros (qptr[B]) the records cover
+  int mb;                 // dims per bfloat16 row (bf16_row_dims(m))
+  int m;                  // real dims
   const uint8_t* V8;      // [v][m8] fp8 (OCP e4m3) codes of V / vscale (PREC_FP8)
   const float* vscale;    // [v] fp8 row scales
   int m8;                 // bytes per fp8 row: m_pad rounded up to 128
@@ -135,13 +148,18 @@ __device__ __forceinline__ void zw_write_row(float2* ZW, int64_t zw_nq, int KT, 
 hipError_t launch_phase1_deep(const P1Args& a, int mode, int hmax, int prec, hipStream_t s);
 hipError_t launch_phase1_fast(const P1Args& a, int mode, int KT, int prec, hipStream_t s);
 hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, int seg_hmax, hipStream_t s);
+// bfloat16 table modes (lists of depth + 8 <= 32, segments <= kSegShort words,
+// rows of at most kBf16MaxDims dims)
+bool phase1_bf16_fits(int mb, int seg_hmax, int depth);
+hipError_t launch_phase1_bf16(const P1Args& a, int mode, int depth, hipStream_t s);
 int phase1_wide_rows();
 hipError_t launch_fix_rows(const P1Args& a, int mode, int count, hipStream_t s);
 hipError_t launch_pair_reduce(const float* partial, int64_t npairs, int rb_max, float* out,
                               int64_t out_ld, int64_t per_row, hipStream_t s);
 hipError_t launch_prep_embeddings(const float* Vin, int64_t v, int m, int m_pad, int l2norm,
                                   float* Vpad, float* vnorm, hipStream_t s);
-hipError_t launch_make_bf16(const float* V, int64_t count, uint16_t* out, hipStream_t s);
+hipError_t launch_make_bf16_rows(const float* V, const float* vnorm, int64_t v, int m, int m_pad, int mb,
+                                 uint16_t* out_row, uint16_t* out_query, float* vres, hipStream_t s);
 hipError_t launch_make_fp8(const float* V, int64_t v, int m_pad, int m8, uint8_t* out, float* scale,
                            hipStream_t s);
 hipError_t launch_validate_csr(const int64_t* ptr, const int32_t* col, const float* val,

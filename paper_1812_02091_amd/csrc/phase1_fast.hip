@@ -485,10 +485,7 @@ static hipError_t launch_fast_prec(const P1Args& a, int mode, int KL, hipStream_
 
 hipError_t launch_phase1_fast(const P1Args& a, int mode, int KL, int prec, hipStream_t s) {
   if (prec == PREC_F32) return launch_fast_prec<PREC_F32>(a, mode, KL, s);
-  if (prec == PREC_BF16) {
-    if (!a.Vb) return hipErrorInvalidValue;
-    return launch_fast_prec<PREC_BF16>(a, mode, KL, s);
-  }
+  if (prec == PREC_BF16) return hipErrorInvalidValue;  // bf16 keys: launch_phase1_bf16
   return hipErrorInvalidValue;
 }
 

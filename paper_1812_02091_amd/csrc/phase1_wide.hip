@@ -982,10 +982,7 @@ hipError_t launch_phase1_wide(const P1Args& a, int mode, int KL, int prec, int s
   if (seg_hmax > kSegLong) return hipErrorInvalidValue;
   if (seg_hmax > kSeg) return prec == PREC_F32 ? launch_wide_prec<PREC_F32, true>(a, mode, KL, s) : hipErrorInvalidValue;
   if (prec == PREC_F32) return launch_wide_prec<PREC_F32>(a, mode, KL, s);
-  if (prec == PREC_BF16) {
-    if (!a.Vb) return hipErrorInvalidValue;
-    return launch_wide_prec<PREC_BF16>(a, mode, KL, s);
-  }
+  if (prec == PREC_BF16) return hipErrorInvalidValue;  // bf16 keys: launch_phase1_bf16
   if (prec == PREC_FP8) {
     if (!a.V8 || !a.vscale || a.m8 % 128 != 0) return hipErrorInvalidValue;
     return launch_wide_prec<PREC_FP8>(a, mode, KL, s);

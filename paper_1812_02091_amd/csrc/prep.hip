@@ -46,19 +46,67 @@ hipError_t launch_prep_embeddings(const float* Vin, int64_t v, int m, int m_pad,
   return hipGetLastError();
 }
 
-// bfloat16 copy, round to nearest even (NaN-free inputs).
-__global__ __launch_bounds__(kThreads) void k_make_bf16(const float* __restrict__ V, int64_t count,
-                                                        uint16_t* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= count) return;
-  const uint32_t u = __float_as_uint(V[i]);
-  const uint32_t rounded = u + 0x7fffu + ((u >> 16) & 1u);
-  out[i] = (uint16_t)(rounded >> 16);
+// bfloat16 rows for the bf16 phase-1 kernel, round to nearest even
+// (finite inputs), in two forms.  Row form (the vocabulary side): dims < m
+// hold -2 v (bf16(-2 v) = -2 bf16(v), exactly), dims m..m+2 hold 1 and dims
+// m+3..m+5 a three-piece split of |v|^2 (each piece the bf16 rounding of
+// what the earlier ones leave: three bf16 significands hold the float32
+// value exactly).  Query form (the query side): dims < m hold v, dims
+// m..m+2 the split of |v|^2 and dims m+3..m+5 hold 1.  The rest are 0, so a
+// row-form row times a query-form row is |v|^2 + |q|^2 - 2 <v_b, q_b>.
+// vres gets |v - bf16(v)| from float64 sums, rounded up.  One wave per row.
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__global__ __launch_bounds__(kThreads) void k_make_bf16_rows(const float* __restrict__ V,
+                                                             const float* __restrict__ vnorm, int64_t v,
+                                                             int m, int m_pad, int mb,
+                                                             uint16_t* __restrict__ out_row,
+                                                             uint16_t* __restrict__ out_query,
+                                                             float* __restrict__ vres) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (r >= v) return;
+  const float* x = V + r * (int64_t)m_pad;
+  uint16_t* o = out_row + r * (int64_t)mb;
+  uint16_t* oq = out_query + r * (int64_t)mb;
+  const float vn = vnorm[r];
+  const float p0 = bf16_val(bf16_rne(vn));
+  const float p1 = bf16_val(bf16_rne(vn - p0));
+  const float p2 = bf16_val(bf16_rne(vn - p0 - p1));
+  double e2 = 0.0;
+  for (int d = lane; d < mb; d += 64) {
+    float y, yq;
+    if (d < m) {
+      const float f = x[d];
+      const uint16_t b = bf16_rne(f);
+      const double e = (double)f - (double)bf16_val(b);
+      e2 += e * e;
+      y = -2.f * bf16_val(b);
+      yq = bf16_val(b);
+    } else if (d < m + 6) {
+      const int t = (d - m) % 3;
+      const float piece = t == 0 ? p0 : (t == 1 ? p1 : p2);
+      y = d < m + 3 ? 1.f : piece;
+      yq = d < m + 3 ? piece : 1.f;
+    } else {
+      y = yq = 0.f;
+    }
+    o[d] = bf16_rne(y);
+    oq[d] = bf16_rne(yq);
+  }
+  for (int k = 32; k > 0; k >>= 1) e2 += __shfl_xor(e2, k);
+  if (lane == 0) vres[r] = (float)(sqrt(e2) * (1.0 + 1e-6)) + 1e-38f;
 }
 
-hipError_t launch_make_bf16(const float* V, int64_t count, uint16_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_make_bf16, dim3((unsigned)((count + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, V, count, out);
+hipError_t launch_make_bf16_rows(const float* V, const float* vnorm, int64_t v, int m, int m_pad, int mb,
+                                 uint16_t* out_row, uint16_t* out_query, float* vres, hipStream_t s) {
+  const int64_t blocks = (v + kThreads / 64 - 1) / (kThreads / 64);
+  hipLaunchKernelGGL(k_make_bf16_rows, dim3((unsigned)blocks), dim3(kThreads), 0, s, V, vnorm, v, m, m_pad, mb,
+                     out_row, out_query, vres);
   return hipGetLastError();
 }
 

@@ -1,19 +1,20 @@
 // Serving engine: continuous batching of a query stream against the resident
 // database (entry points lcemd_server_* in include/lcemd.h).
 //
-// Submitted queries wait in a FIFO.  A worker thread owns the context while
-// the server runs.  It admits queries into a free lane -- a stream with its
-// own preallocated device and pinned host buffers for up to B queries and W
-// words -- and launches that lane's batch: phase 1 (tables), the exact
-// redo of uncertified bf16 rows, phase 2 on a persistent kernel fed by
-// per-XCD work counters, the D2Q candidate selection, Q2D for the
-// candidates, the symmetric max and top-l.  All of it has fixed launch
-// shapes (padding slots are empty queries; the live query count is read
-// from device memory), so with use_graph it is captured once per lane as a
-// hipGraph and replayed for every batch.  With two or more lanes, batches
-// that arrive while others run are admitted (once half a batch is waiting)
-// and their work overlaps on the device; a query whose symmetric top-l certificate fails (or whose lists
-// overflowed) is finished by the exact widening path of lcemd_topl.
+// The memory budget is split at start into K lanes: a lane is a stream with
+// its own preallocated device and pinned host buffers for up to B queries
+// and W words.  Submitted queries wait in one FIFO (admission.h); a worker
+// thread owns the context while the server runs, and whenever a lane is free
+// and queries wait it hands the lane the FIFO head's queries at once and
+// launches the lane's batch: phase 1 (tables), the exact redo of
+// uncertified bf16 rows, phase 2 on a persistent kernel fed by per-XCD work
+// counters, the D2Q candidate selection, Q2D for the candidates, the
+// symmetric max and top-l.  Up to K batches overlap on the device.  All of a
+// batch has fixed launch shapes (padding slots are empty queries; the live
+// query count is read from device memory), so with use_graph it is captured
+// once per lane as a hipGraph and replayed for every batch.  A query whose
+// symmetric top-l certificate fails (or whose lists overflowed) is
+// finished by the exact widening path of lcemd_topl.
 //
 // Each query's result depends only on that query: tables, per-document
 // sums and the top-l selection are computed per query in a fixed order, and
@@ -29,6 +30,7 @@
 #include <unordered_set>
 #include <vector>
 
+#include "admission.h"
 #include "context.h"
 
 using namespace lcemd;
@@ -45,6 +47,7 @@ struct Pending {
   std::vector<int32_t> col;
   std::vector<float> val;
   double t_submit;
+  int words;
 };
 
 struct Done {
@@ -72,6 +75,8 @@ struct Lane {
   uint64_t* seltmp = nullptr;
   float* q2dv = nullptr;
   float* partial = nullptr;
+  float4* rinfo = nullptr;  // bf16 phase-1 records (lane-owned: graphs capture the pointers)
+  float4* qinfo = nullptr;
   int64_t* idx = nullptr;
   float* dist = nullptr;
   int* flags = nullptr;
@@ -99,12 +104,11 @@ struct lcemd_server {
   int prec = LCEMD_FP32;
   int KT = 1, depth_pair = 1, use = 0, cld = 0, l = 0;
   int B = 1, W = LCEMD_SERVE_MAX_HIST;
-  bool continuous = true;
   std::vector<Lane> lanes;
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Pending> pending;
+  lcemd_serve::Admission<Pending>* adm = nullptr;  // FIFO + free lanes (guarded by mu)
   std::unordered_map<uint64_t, Done> done;
   std::unordered_set<uint64_t> live;  // submitted, not yet waited for
   uint64_t next_ticket = 1;
@@ -136,7 +140,7 @@ int halloc(lcemd_ctx* c, T*& p, size_t count) {
 
 void free_lane(Lane& L) {
   if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
-  void* dev[] = {L.qptr, L.qcol, L.qval, L.nq, L.ints, L.ctr, L.fixl, L.ZW, L.d2q, L.cand, L.seltmp, L.q2dv, L.partial, L.idx, L.dist, L.flags};
+  void* dev[] = {L.qptr, L.qcol, L.qval, L.nq, L.ints, L.ctr, L.fixl, L.ZW, L.d2q, L.cand, L.seltmp, L.q2dv, L.partial, L.rinfo, L.qinfo, L.idx, L.dist, L.flags};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {L.h_qptr, L.h_qcol, L.h_qval, L.h_nq, L.h_idx, L.h_dist, L.h_flags, L.h_ints};
@@ -189,6 +193,9 @@ int issue(lcemd_server* s, Lane& L) {
     a.fix_count = L.ints + 9;
     a.fix_list = L.fixl;
     a.fix_cap = kFixCapLane;
+    a.rinfo = L.rinfo;
+    a.qinfo = L.qinfo;
+    a.qnnz = s->W;  // the lane's word capacity (padding words are never read)
     // ICT lists stop at 16 entries as in lcemd_topl; deeper rows go to the
     // exact redo below (tables hold s->KT entries)
     const int list_depth = s->cfg.method == LCEMD_ICT ? std::min(s->KT, kIctList) : s->KT;
@@ -230,6 +237,7 @@ int setup_lane(lcemd_server* s, Lane& L) {
       (rc = dalloc(c, L.seltmp, select_tmp_elems(B, n, s->cld), "lane")) ||
       (rc = dalloc(c, L.q2dv, B * s->use, "lane")) ||
       (rc = dalloc(c, L.partial, B * s->use * rbcap, "lane")) ||
+      (rc = dalloc(c, L.rinfo, c->v_used, "lane")) || (rc = dalloc(c, L.qinfo, W, "lane")) ||
       (rc = dalloc(c, L.idx, B * s->l, "lane")) || (rc = dalloc(c, L.dist, B * s->l, "lane")) ||
       (rc = dalloc(c, L.flags, B, "lane")))
     return rc;
@@ -333,13 +341,17 @@ void finish_lane(lcemd_server* s, Lane& L) {
 
 void worker_main(lcemd_server* s) {
   (void)hipSetDevice(s->ctx->device);
+  std::vector<Pending> batch;
   while (true) {
     bool any_busy = false;
-    for (Lane& L : s->lanes) {
+    for (int li = 0; li < (int)s->lanes.size(); ++li) {
+      Lane& L = s->lanes[li];
       if (!L.busy) continue;
       const hipError_t q = hipEventQuery(L.ev);
       if (q == hipSuccess) {
         finish_lane(s, L);
+        std::lock_guard<std::mutex> g(s->mu);
+        s->adm->done(li);
       } else if (q != hipErrorNotReady) {
         std::lock_guard<std::mutex> g(s->mu);
         s->dead = LCEMD_E_HIP;
@@ -347,53 +359,40 @@ void worker_main(lcemd_server* s) {
         for (const Pending& p : L.batch) s->done[p.ticket] = Done{{}, {}, 0.0, LCEMD_E_HIP};
         L.batch.clear();
         L.busy = false;
+        s->adm->done(li);
         s->cv_done.notify_all();
       } else {
         any_busy = true;
       }
     }
-    Lane* freeL = nullptr;
+    int lane = -1;
     {
       std::unique_lock<std::mutex> g(s->mu);
       if (s->dead) {
-        for (const Pending& p : s->pending) s->done[p.ticket] = Done{{}, {}, 0.0, s->dead};
-        s->pending.clear();
+        for (const Pending& p : s->adm->queue()) s->done[p.ticket] = Done{{}, {}, 0.0, s->dead};
+        s->adm->queue().clear();
         s->cv_done.notify_all();
         if (!any_busy) break;
       }
-      if (s->stopping && s->pending.empty() && !any_busy) break;
-      // an idle device takes whatever is queued; while a batch runs, a
-      // second lane starts only once half a batch is waiting (a few
-      // queries finish sooner after the running batch than beside it)
-      if (!s->pending.empty() &&
-          (!any_busy || (s->continuous && (int)s->pending.size() >= std::max(1, s->B / 2)))) {
-        for (Lane& L : s->lanes)
-          if (!L.busy) {
-            freeL = &L;
-            break;
-          }
-      }
-      if (freeL) {
-        // admission: FIFO, up to B queries and W words per batch
-        int words = 0;
-        while (!s->pending.empty() && (int)freeL->batch.size() < s->B &&
-               words + (int)s->pending.front().col.size() <= s->W) {
-          words += (int)s->pending.front().col.size();
-          freeL->batch.push_back(std::move(s->pending.front()));
-          s->pending.pop_front();
-        }
-      } else if (!any_busy) {
-        s->cv_work.wait(g, [s] { return s->stopping || !s->pending.empty(); });
+      if (s->stopping && s->adm->waiting() == 0 && !any_busy) break;
+      // continuous batching: a free lane takes the FIFO head's queries at once
+      if (!s->dead) lane = s->adm->next(batch);
+      if (lane < 0 && !any_busy) {
+        s->cv_work.wait(g, [s] { return s->stopping || s->adm->waiting() > 0; });
         continue;
       }
     }
-    if (freeL) {
-      const int rc = launch_batch(s, *freeL);
+    if (lane >= 0) {
+      Lane& L = s->lanes[lane];
+      L.batch = std::move(batch);
+      batch.clear();
+      const int rc = launch_batch(s, L);
       if (rc) {
         std::lock_guard<std::mutex> g(s->mu);
-        for (const Pending& p : freeL->batch) s->done[p.ticket] = Done{{}, {}, 0.0, rc};
-        freeL->batch.clear();
-        freeL->busy = false;
+        for (const Pending& p : L.batch) s->done[p.ticket] = Done{{}, {}, 0.0, rc};
+        L.batch.clear();
+        L.busy = false;
+        s->adm->done(lane);
         s->dead = rc;
         s->cv_done.notify_all();
       }
@@ -421,7 +420,8 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
     return fail(c, LCEMD_E_INVALID_ARG, "unknown precision %d", cfg->precision);
   if (cfg->l < 1 || cfg->l > LCEMD_MAX_L || cfg->l > c->n) return fail(c, LCEMD_E_INVALID_ARG, "bad l");
   if (cfg->max_slots < 1) return fail(c, LCEMD_E_INVALID_ARG, "max_slots must be >= 1");
-  for (int i = 0; i < 5; ++i)
+  if (cfg->lanes < 0 || cfg->lanes > 16) return fail(c, LCEMD_E_INVALID_ARG, "lanes must be 0..16");
+  for (int i = 0; i < 4; ++i)
     if (cfg->reserved[i]) return fail(c, LCEMD_E_INVALID_ARG, "reserved fields must be 0");
   if (c->db_hmax > LCEMD_SERVE_MAX_HIST)
     return fail(c, LCEMD_E_CAPACITY, "serving needs database histograms of at most %d words (longest: %d)",
@@ -444,24 +444,28 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   s->cld = s->use < c->n ? s->use + 1 : s->use;
   if (s->cld > kSelectBuf / 2) s->use = kSelectBuf / 2 - 1, s->cld = s->use + 1;
   // admission by device memory: lanes x slots x per-query state <= budget
-  const int nlanes = cfg->use_graph ? 2 : 1;
-  s->continuous = nlanes > 1;
+  const int nlanes = cfg->lanes > 0 ? cfg->lanes : (cfg->use_graph ? 4 : 1);
   const double per_q = (double)c->v_used * zw_pairs(s->KT) * 16 + (double)c->n * 4 + (double)s->cld * 8 +
-                       (double)s->use * 4 * (1 + (LCEMD_SERVE_MAX_HIST + kRows - 1) / kRows) + 64.0 * s->l;
+                       (double)s->use * 4 * (1 + (LCEMD_SERVE_MAX_HIST + kRows - 1) / kRows) + 64.0 * s->l +
+                       (double)LCEMD_SERVE_MAX_HIST * 32;
+  const double per_lane = (double)c->v_used * 16 + (double)kFixCapLane * 8 +
+                          (double)select_tmp_elems(cfg->max_slots, c->n, s->cld) * 8;
   const int64_t budget = cfg->memory_budget > 0 ? cfg->memory_budget : (int64_t(4) << 30);
-  const int64_t fit = (int64_t)(budget / (per_q * nlanes));
+  const int fit = lcemd_serve::plan_slots(budget, per_q, per_lane, nlanes, cfg->max_slots);
   if (fit < 1) {
     delete s;
-    return fail(c, LCEMD_E_CAPACITY, "memory budget %lld B holds no query (%.0f B per query)",
-                (long long)budget, per_q);
+    return fail(c, LCEMD_E_CAPACITY, "memory budget %lld B holds no query (%.0f B per query, %d lanes)",
+                (long long)budget, per_q, nlanes);
   }
-  s->B = (int)std::min<int64_t>(cfg->max_slots, fit);
+  s->B = fit;
   s->W = cfg->max_batch_words > 0 ? std::max(cfg->max_batch_words, (int32_t)LCEMD_SERVE_MAX_HIST)
                                    : s->B * LCEMD_SERVE_MAX_HIST;
+  s->adm = new lcemd_serve::Admission<Pending>(nlanes, s->B, s->W);
   s->lanes.resize(nlanes);
   for (Lane& L : s->lanes) {
     if ((rc = setup_lane(s, L))) {
       for (Lane& M : s->lanes) free_lane(M);
+      delete s->adm;
       delete s;
       return rc;
     }
@@ -485,14 +489,16 @@ int lcemd_server_submit(lcemd_server* s, const int32_t* col, const float* val, i
   p.col.assign(col, col + h);
   p.val.assign(val, val + h);
   p.t_submit = now_s();
+  p.words = h;
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stopping) return LCEMD_E_INVALID_ARG;
     if (s->dead) return s->dead;
+    if (!s->adm->fits(h)) return LCEMD_E_CAPACITY;
     p.ticket = s->next_ticket++;
     *ticket = p.ticket;
     s->live.insert(p.ticket);
-    s->pending.push_back(std::move(p));
+    s->adm->push(std::move(p));
   }
   s->cv_work.notify_one();
   return LCEMD_OK;
@@ -527,6 +533,7 @@ void lcemd_server_stop(lcemd_server* s) {
     if (L.stream) (void)hipStreamSynchronize(L.stream);
     free_lane(L);
   }
+  delete s->adm;
   delete s;
 }
 

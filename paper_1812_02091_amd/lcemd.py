@@ -54,8 +54,8 @@ class lcemd_phase_time(C.Structure):
 class lcemd_server_cfg(C.Structure):
     _fields_ = [("method", C.c_int32), ("k", C.c_int32), ("precision", C.c_int32),
                 ("l", C.c_int32), ("max_slots", C.c_int32), ("max_batch_words", C.c_int32),
-                ("memory_budget", C.c_int64), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("memory_budget", C.c_int64), ("use_graph", C.c_int32), ("lanes", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 # every symbol the header declares, with its ctypes signature
@@ -90,6 +90,9 @@ _SIGS = {
     "lcemd_server_stop": (None, [C.c_void_p]),
     "lcemd_check_histograms": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                          C.c_int, C.c_char_p, C.c_size_t]),
+    "lcemd_serve_sim": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int64, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None
@@ -351,7 +354,7 @@ class Server:
     it runs, the context belongs to the server's worker thread."""
 
     def __init__(self, ctx: "Context", method="act", k=8, precision="fp32", l=16,
-                 max_slots=64, max_batch_words=0, memory_budget=0, use_graph=True):
+                 max_slots=64, max_batch_words=0, memory_budget=0, use_graph=True, lanes=0):
         self.lib = ctx.lib
         cfg = lcemd_server_cfg()
         cfg.method = METHOD[method] if isinstance(method, str) else int(method)
@@ -362,6 +365,7 @@ class Server:
         cfg.max_batch_words = int(max_batch_words)
         cfg.memory_budget = int(memory_budget)
         cfg.use_graph = int(bool(use_graph))
+        cfg.lanes = int(lanes)
         h = C.c_void_p()
         rc = self.lib.lcemd_server_start(ctx.h, C.byref(cfg), C.byref(h))
         if rc != OK:
@@ -411,6 +415,26 @@ def check_histograms(rowptr, col, val, v: int, require_normalized: bool = True):
     rc = lib.lcemd_check_histograms(C.c_void_p(p.ptr), C.c_void_p(c.ptr), C.c_void_p(w.ptr),
                                     p.obj.shape[0] - 1, int(v), int(require_normalized), msg, 512)
     return rc, msg.value.decode()
+
+
+def serve_sim(arrival_s, words, lanes: int, max_slots: int, max_words: int, budget: int,
+              per_query_bytes: float, t_fixed_s: float, t_per_query_s: float):
+    """The serving admission policy on the host with a fake executor
+    (lcemd_serve_sim): returns (slots per lane, status, lane, launch, start,
+    finish) arrays, one entry per query."""
+    lib = load_library()
+    a = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    w = np.ascontiguousarray(words, dtype=np.int32)
+    nq = a.shape[0]
+    status, lane, launch = (np.empty(nq, dtype=np.int32) for _ in range(3))
+    start, finish = np.empty(nq, dtype=np.float64), np.empty(nq, dtype=np.float64)
+    rc = lib.lcemd_serve_sim(nq, a.ctypes.data, w.ctypes.data, int(lanes), int(max_slots), int(max_words),
+                             int(budget), float(per_query_bytes), float(t_fixed_s), float(t_per_query_s),
+                             status.ctypes.data, lane.ctypes.data, launch.ctypes.data, start.ctypes.data,
+                             finish.ctypes.data)
+    if rc < 0:
+        raise LcemdError(rc, "serve_sim")
+    return rc, status, lane, launch, start, finish
 
 
 def open_context(V, db_rowptr, db_col, db_val, device: int = 0, l2_normalize: bool = False,
