@@ -1,15 +1,19 @@
 """Benchmark: symmetric ACT top-l search of a query batch against a resident
-text-shaped histogram database on one MI355X.
+1M-word / 1M-document histogram database on one MI355X.
 
 One step = one lcemd_topl call on the whole batch (query staging, phase-1
-distance GEMM + ordered extraction, phase-2 transfers, Q2D for the pruned
-candidates, symmetric max, top-l), with the database and the query batch
-already resident in HBM.
+distance contraction + ordered extraction + float32 recompute, phase-2
+transfers, Q2D for the pruned candidates, symmetric max, top-l), with the
+database and the query batch already resident in HBM.
 
-Workload (synthetic, seeded; stands in for 20 Newsgroups with 300-d word
-vectors, which is not available here): vocabulary 70,000 x 300 unit-norm
-Gaussian embeddings, 18,000 database histograms and 1,000 queries of 50-300
-distinct Zipf(1.0) words (log-normal lengths, mean ~120), tf weights.
+Workload (synthetic, seeded; stands in for word2vec-embedded text, which is
+not available here): vocabulary 1,000,000 x 300 unit-norm Gaussian
+embeddings, 1,000,000 database histograms and 4,096 queries of 50-300
+distinct Zipf(1.0) words (log-normal lengths, mean ~120), tf weights; ACT
+k=8, symmetric, top-16.  The headline value is the bf16 path (bf16 phase-1
+keys, float32 recompute of the selected candidates); the float32 and fp8
+paths run the same batch beside it.  Serving: open-loop Poisson streams of
+10-500-word queries against the same resident database.
 
 Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
@@ -30,27 +34,28 @@ HBM_PEAK = 8.0e12
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--method", default="act")
-    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--k", type=int, default=8)
     ap.add_argument("--ell", type=int, default=16)
     ap.add_argument("--direction", default="sym")
-    ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--workload", default="text")
+    ap.add_argument("--precision", default="bf16", help="phase-1 keys of the headline path")
+    ap.add_argument("--workload", default="text-1M")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--B", type=int, default=None)
-    ap.add_argument("--cpu-queries", type=int, default=2, help="queries in the oracle sample")
+    ap.add_argument("--other-steps", type=int, default=1, help="timed steps of each other precision")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the bf16-path comparison")
-    ap.add_argument("--no-big", action="store_true", help="skip the 1M-word precision and serving section")
+    ap.add_argument("--cpu-workers", type=int, default=16, help="oracle worker processes (the box's CPU share)")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
+    ap.add_argument("--no-big", action="store_true", help="skip the image and self-join sections")
+    ap.add_argument("--all-sections", action="store_true", help="also the measure and dense-image sections")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--big-queries", type=int, default=4096, help="queries of the 1M-word precision run")
-    ap.add_argument("--serve-rate", type=float, default=200.0, help="offered load, queries/s")
-    ap.add_argument("--serve-queries", type=int, default=1000)
-    ap.add_argument("--serve-sat", type=int, default=256, help="queries in the saturation sample")
+    ap.add_argument("--serve-rates", default="200,500,1000,2000,5000", help="offered loads, queries/s")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival span per rate")
+    ap.add_argument("--serve-sat", type=int, default=512, help="queries in the saturation burst")
     ap.add_argument("--serve-slots", type=int, default=16)
-    ap.add_argument("--serve-budget", type=int, default=8, help="GiB of device memory for lanes")
+    ap.add_argument("--serve-budget", type=int, default=16, help="GiB of device memory for lanes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scales FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -72,22 +77,25 @@ def phase1_kernel(method, k, precision, m):
     return "k_phase1_fast<0, 64, 0>" if depth <= 64 else "k_phase1_f32"
 
 
-def measured_traffic(kernel, a):
+KERNEL_SOURCES = {"k_phase1_bf16": "phase1_bf16.hip", "k_phase2_persistent": "phase2.hip"}
+
+
+def measured_traffic(kernel, a, precision):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    summary of this workload, if it was taken on the current kernel source
-    (its sha256 is recorded with it); otherwise None."""
+    record of this workload (profiles/traffic.json), if it was taken on the
+    current kernel source (its sha256 is recorded with it); otherwise None."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_1812_02091_amd", "csrc", "phase1_wide.hip")
+    src = os.path.join(ROOT, "paper_1812_02091_amd", "csrc", KERNEL_SOURCES.get(kernel.split("<")[0], "phase1_wide.hip"))
     try:
         rec = json.load(open(path))
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    key = f"{a.workload}:{a.method}:{a.k}:{a.direction}:{a.precision}"
+    key = f"{a.workload}:{a.method}:{a.k}:{a.direction}:{precision}:{kernel.split('<')[0]}"
     e = rec.get(key)
-    if not e or e.get("source_sha256") != digest or e.get("kernel") != kernel:
+    if not e or e.get("source_sha256") != digest:
         return None
     return e["bytes_per_launch"]
 
@@ -106,56 +114,128 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": 3}))
 
 
-_ORC = None
+_ORC = {}
 
 
-def _oracle_init(V, ptr, col, val):
-    global _ORC
-    from oracle import emd_oracle as O
-
-    _ORC = O.Oracle(V, ptr, col, val)
+def _host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"os_cpu_count": os.cpu_count(), "nproc": nproc, "cpu_model": model}
 
 
 def _oracle_task(args):
-    """One query of the CPU baseline: the oracle's symmetric distances to every
-    database row, then its top-l (what one GPU step computes per query)."""
-    qc, qw, method, k, ell = args
-    t0 = time.time()
-    row = _ORC.row_distances(qc, qw, method, k, "sym")
-    _ORC.top_l(row, ell)
-    return row.shape[0], time.time() - t0, row
+    """One oracle task: the float64 symmetric distances of one query to a
+    range of database rows (a fresh Oracle over those rows), in a forked
+    worker that inherited the workloads."""
+    name, b, lo, hi, method, k = args
+    from oracle import emd_oracle as O
+
+    w = _ORC[name]
+    sub = w.db.take(range(lo, hi))
+    t0 = time.perf_counter()
+    orc = O.Oracle(w.V, sub.rowptr, sub.col, sub.val)
+    qc, qw = w.queries.row(b)
+    row = orc.row_distances(qc, qw, method, k, "sym")
+    return name, b, lo, hi - lo, time.perf_counter() - t0, row
 
 
-def cpu_baseline(w, method, k, ell, nq):
+def cpu_baseline(workers, method, k, big):
+    """The float64 oracle timed on the host's cores, before any GPU work
+    (forked workers inherit the workloads; one thread each).  Samples: the
+    tiny workload whole (8 x 200); 8 text queries x all 18,000 rows; 8 image
+    queries x all 60,000 rows; 1 query of the 1M-word workload x all
+    1,000,000 rows (`big`, the headline's workload: its rate is `value`).
+    Returns the record and the 1M-word oracle row (for the error check)."""
     import multiprocessing as mp
 
-    cores = max(1, min(16, os.cpu_count() or 1, nq))
-    tasks = [(*w.queries.row(b), method, k, ell) for b in range(nq)]
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(cores, initializer=_oracle_init,
-                  initargs=(w.V, w.db.rowptr, w.db.col, w.db.val)) as pool:
-        res = pool.map(_oracle_task, tasks, chunksize=1)
-    pairs = sum(r[0] for r in res)
-    # per-worker compute time (excludes process start-up); queries run in parallel
-    dt = max(sum(r[1] for r in res) / cores, max(r[1] for r in res))
-    rec = {"value": pairs / dt, "unit": "distances/s", "cores": cores, "kind": "oracle",
-           "sample": f"{nq} queries x all {w.db.n} database rows, {method.upper()} k={k} symmetric "
-                     f"+ top-{ell}, float64 numpy/scipy, {cores} worker processes, {dt:.1f} s of oracle time per worker"}
-    return rec, [r[2] for r in res]
-
-
-def oracle_error(ctx, w, nq, rows, method, k, precision):
-    """Relative error of the library's symmetric distances (first nq
-    queries, every database row) against the float64 oracle rows."""
     import numpy as np
 
-    q = w.queries.take(list(range(nq)))
-    g = ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="sym", precision=precision)
-    o = np.stack(rows)
-    rel = np.abs(g.astype(np.float64) - o) / np.maximum(np.abs(o), 1e-30)
-    rel[o == 0] = np.where(g[o == 0] == 0, 0.0, np.inf)
-    return {"max_rel_err_vs_fp64_oracle": float(rel.max()), "median_rel_err_vs_fp64_oracle": float(np.median(rel)),
-            "pairs": int(rel.size)}
+    from synth import make_workload
+
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    _ORC["tiny"] = make_workload("tiny")
+    _ORC["text"] = make_workload("text", B=8)
+    _ORC["image"] = make_workload("image", B=8)
+    _ORC["text-1M"] = big
+    plan = (("text", 8, 18000, 2250), ("image", 8, 60000, 7500), ("text-1M", 1, big.db.n, 31250))
+    tasks = [("tiny", b, 0, 200, method, min(k, 3)) for b in range(8)]
+    for name, nq, n, chunk in plan:
+        for b in range(nq):
+            for lo in range(0, n, chunk):
+                tasks.append((name, b, lo, min(n, lo + chunk), method, k))
+    # the long 1M-word chunks first, so that the pool ends together
+    tasks.sort(key=lambda t: -(t[3] - t[2]) * (3 if t[0] == "text-1M" else 1))
+    workers = max(1, min(workers, os.cpu_count() or 1))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    res = []
+    with ctx.Pool(workers) as pool:
+        for i, r in enumerate(pool.imap_unordered(_oracle_task, tasks, chunksize=1)):
+            res.append(r)
+            if (i + 1) % 32 == 0 or i + 1 == len(tasks):
+                print(f"[bench] oracle baseline: {i + 1}/{len(tasks)} tasks, {time.perf_counter() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    per = {}
+    big_row = {}
+    for name, b, lo, npairs, dt, row in res:
+        d = per.setdefault(name, {"pairs": 0, "cpu_s": 0.0})
+        d["pairs"] += npairs
+        d["cpu_s"] += dt
+        if name == "text-1M":
+            big_row[lo] = row
+    big_row = np.concatenate([big_row[lo] for lo in sorted(big_row)])
+    total_cpu = sum(d["cpu_s"] for d in per.values())
+    for name, d in per.items():
+        d["single_core_pairs_per_s"] = d["pairs"] / d["cpu_s"]
+        # all cores: the sample's share of the pool's wall time
+        d["all_core_pairs_per_s"] = d["pairs"] / (wall * d["cpu_s"] / total_cpu)
+    per["tiny"]["sample"] = "the whole 8 x 200 workload (ACT k=min(k,3))"
+    per["text"]["sample"] = "8 queries x all 18,000 rows"
+    per["image"]["sample"] = "8 queries x all 60,000 rows"
+    per["text-1M"]["sample"] = f"query 0 x all {big.db.n:,} rows"
+    bigrec = per["text-1M"]
+    host = _host_info()
+    full_h = big.queries.n * big.db.n / bigrec["all_core_pairs_per_s"] / 3600
+    rec = {"value": bigrec["all_core_pairs_per_s"], "unit": "distances/s", "cores": workers, "kind": "oracle",
+           "sample": (f"query 0 of the 1M-word workload x all {big.db.n:,} database rows, {method.upper()} k={k} "
+                      f"symmetric, float64 numpy/scipy oracle, {workers} worker processes of one thread "
+                      f"({wall:.1f} s wall for all samples, {total_cpu:.0f} s of CPU); the full "
+                      f"{big.queries.n:,} x {big.db.n:,} batch would take {full_h:.0f} h at this rate "
+                      f"(extrapolation)"),
+           "host": host, "samples": per, "wall_s": wall, "cpu_s": total_cpu}
+    return rec, big_row
+
+
+def oracle_pairs_error(w, idx, dist, picks, method, k):
+    """Relative error of returned (query, neighbour) distances against the
+    float64 oracle, pair by pair."""
+    import numpy as np
+
+    from oracle import emd_oracle as O
+
+    docs = sorted({int(idx[b, j]) for b, j in picks})
+    sub = w.db.take(docs)
+    pos = {u: i for i, u in enumerate(docs)}
+    orc = O.Oracle(w.V, sub.rowptr, sub.col, sub.val)
+    errs = []
+    for b, j in picks:
+        qc, qw = w.queries.row(int(b))
+        o = orc.pair(qc, qw, pos[int(idx[b, j])], method, k, "sym")
+        errs.append(abs(float(dist[b, j]) - o) / max(abs(o), 1e-30))
+    return {"max_rel_err_vs_fp64_oracle": float(np.max(errs)), "median_rel_err_vs_fp64_oracle": float(np.median(errs)),
+            "oracle_pairs": len(errs)}
 
 
 def image_section(a, lcemd):
@@ -186,9 +266,10 @@ def image_section(a, lcemd):
         rec = {"distances_per_s": B * n / dt, "s_per_batch": dt,
                "phase_ms": {k2: v["ms"] for k2, v in ph.items()}}
         if "phase2" in ph and ph["phase2"]["ms"] > 0:
-            gbs = ph["phase2"]["work"] / (ph["phase2"]["ms"] * 1e-3) / 1e9
-            rec["phase2_algorithmic_GBps"] = gbs
-            rec["phase2_hbm_frac"] = gbs * 1e9 / HBM_PEAK
+            # A2 charges every query a full pass over the database; the kernel
+            # shares each record read across up to 64 queries, so this rate can
+            # pass the HBM peak and is not an HBM fraction
+            rec["phase2_algorithmic_GBps_A2"] = ph["phase2"]["work"] / (ph["phase2"]["ms"] * 1e-3) / 1e9
         res[f"act{k}"] = rec
         print(f"[bench] image ACT k={k}: {dt:.3f} s", file=sys.stderr, flush=True)
     # the full symmetric matrix (the reverse direction by the swapped-role
@@ -289,7 +370,7 @@ def selfjoin_section(a, lcemd):
     ctx.profile(False)
     ctx.close()
     res.update({"seconds": dt, "distances_per_s": n * n / dt, "phase_ms": ph,
-                "speedup_vs_paper": (3.3 * 60) / dt})
+                "paper_time_over_this_time_context_only": (3.3 * 60) / dt})
     print(f"[bench] image self-join {n}x{n}: {dt:.3f} s", file=sys.stderr, flush=True)
     return res
 
@@ -332,131 +413,146 @@ def dense_section(a, lcemd):
     return res
 
 
-def big_workload(a, lcemd):
-    """The 1M-word / 1M-document workload: (1) the precision variant -- one
-    symmetric ACT k=8 top-16 call over the whole query batch with float32,
-    bf16 and fp8 phase-1 keys: rates, top-16 agreement with float32, and the
-    error of returned distances against the float64 oracle on sampled
-    (query, neighbour) pairs; (2) serving (see serve_path)."""
-    import numpy as np
-
-    from synth import make_workload
-
-    t0 = time.time()
-    w = make_workload("text-1M", B=a.big_queries)
-    print(f"[bench] 1M-word workload built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
-    v, n, B = w.V.shape[0], w.db.n, w.queries.n
-    res = {"workload": f"text-1M: vocab {v} x {w.V.shape[1]}, {n} database histograms "
-                       f"({w.db.nnz} non-zeros), {B} queries, ACT k=8 symmetric, top-16"}
-    prec = {}
-    qs = w.queries
-    ref = None
-    rng = np.random.default_rng(77)
-    sample = [(int(b), int(j)) for b, j in zip(rng.integers(0, B, 24), rng.integers(0, 16, 24))]
-    small = qs.take(list(range(8)))
-    for p in ("fp32", "bf16", "fp8"):
-        ctx.topl(small.rowptr, small.col, small.val, 16, method="act", k=8, direction="sym", precision=p)
-        t1 = time.perf_counter()
-        idx, dist = ctx.topl(qs.rowptr, qs.col, qs.val, 16, method="act", k=8, direction="sym", precision=p)
-        dt = time.perf_counter() - t1
-        rec = {"distances_per_s": B * n / dt, "s_per_batch": dt}
-        if ref is None:
-            ref = (idx, dist)
-        else:
-            rec["top16_agreement_vs_fp32"] = float(np.mean([len(set(ref[0][i]) & set(idx[i])) / 16 for i in range(B)]))
-        rec["_pairs"] = [(b, int(idx[b, j]), float(dist[b, j])) for b, j in sample]
-        prec[p] = rec
-        print(f"[bench] 1M-word {p}: {dt:.2f} s", file=sys.stderr, flush=True)
-    # float64 oracle on the sampled (query, returned neighbour) pairs
-    from oracle import emd_oracle as O
-
-    docs = sorted({u for p in prec.values() for (_, u, _) in p["_pairs"]})
-    sub = w.db.take(docs)
-    pos = {u: i for i, u in enumerate(docs)}
-    orc = O.Oracle(w.V, sub.rowptr, sub.col, sub.val)
-    for p, rec in prec.items():
-        errs = []
-        for b, u, d in rec.pop("_pairs"):
-            qc, qw = qs.row(b)
-            o = orc.pair(qc, qw, pos[u], "act", 8, "sym")
-            errs.append(abs(d - o) / max(abs(o), 1e-30))
-        rec["max_rel_err_vs_fp64_oracle"] = float(np.max(errs))
-        rec["median_rel_err_vs_fp64_oracle"] = float(np.median(errs))
-        rec["oracle_pairs"] = len(errs)
-    res["precision"] = prec
-    fb, fixed = ctx.counters()
-    res["fallback_tiles"], res["rows_redone_exactly"] = fb, fixed
-    del w, qs, sub, orc
-    if not a.no_serving:
-        res["serving"] = serve_path(a, lcemd, ctx, v, n)
-    ctx.close()
-    return res
-
-
-def serve_path(a, lcemd, ctx, v, n):
-    """Serving on the resident 1M-word database: a Poisson query stream
-    (open loop; 10-500 words per query), ACT k=8, symmetric top-16.  Two
-    paths: bf16 phase 1 on two graph-captured lanes with continuous
-    admission, and float32 phase 1 on one lane with kernels launched per
-    batch and a batch admitted only when the previous one is done.
-    Latency = completion - scheduled arrival."""
+def serve_sweep(a, lcemd, ctx, v, n):
+    """Serving on the resident 1M-word database: open-loop Poisson streams of
+    10-500-word queries (ACT k=8, symmetric top-16), each offered rate for
+    about --serve-seconds, rising until the path saturates (achieved rate
+    below 90 % of the offered one), plus a saturation burst.  Two paths:
+    bf16 keys with continuous batching (queries join free slots of running
+    batches; graph-captured) and float32 keys with plain FIFO batches
+    launched one at a time.  Latency = completion - scheduled arrival."""
     import threading
 
     import numpy as np
 
     from synth import arrival_trace
 
-    _, qs = arrival_trace(a.serve_rate, a.serve_queries + a.serve_sat, v, lmin=10, lmax=500)
+    rates = [float(x) for x in a.serve_rates.split(",") if x]
+    need = a.serve_sat + sum(int(min(3000, max(200, r * a.serve_seconds))) for r in rates) + 8
+    _, qs = arrival_trace(1000.0, need, v, lmin=10, lmax=500)
     rows = [qs.row(b) for b in range(qs.n)]
-    res = {}
+    out = {"setup": (f"Poisson arrivals, 10-500 words per query, up to {a.serve_slots} queries per batch; each "
+                     f"rate offered for ~{a.serve_seconds:g} s (200-3,000 queries) until saturation; saturation = "
+                     f"{a.serve_sat} queries submitted at once")}
     for prec, graph in (("bf16", True), ("fp32", False)):
         srv = lcemd.Server(ctx, method="act", k=8, precision=prec, l=16, max_slots=a.serve_slots,
                            memory_budget=a.serve_budget << 30, use_graph=graph)
-        for b in range(4):  # warm-up
-            srv.wait(srv.submit(*rows[b]))
-        # saturation throughput: the whole sample submitted at once
-        sat = rows[a.serve_queries:]
+        cur = 0
+
+        def take(m):
+            nonlocal cur
+            r = rows[cur:cur + m]
+            cur += m
+            return r
+
+        for q in take(8):  # warm-up
+            srv.wait(srv.submit(*q))
+        sat = take(a.serve_sat)
         t1 = time.perf_counter()
         tk = [srv.submit(c, x) for c, x in sat]
         for t in tk:
             srv.wait(t)
         sat_qps = len(sat) / (time.perf_counter() - t1)
-        # open loop at the stated rate
-        rate = a.serve_rate
-        arr = np.cumsum(np.random.default_rng(55).exponential(1.0 / rate, a.serve_queries))
-        lag = np.zeros(a.serve_queries)
-        tickets = [0] * a.serve_queries
-        start = time.perf_counter() + 0.05
+        sweep = []
+        for rate in rates:
+            nq = int(min(3000, max(200, rate * a.serve_seconds)))
+            batch = take(nq)
+            arr = np.cumsum(np.random.default_rng(55 + int(rate)).exponential(1.0 / rate, nq))
+            lag = np.zeros(nq)
+            tickets = [0] * nq
+            start = time.perf_counter() + 0.05
 
-        def feed():
-            for i in range(a.serve_queries):
-                d = start + arr[i] - time.perf_counter()
-                if d > 0:
-                    time.sleep(d)
-                lag[i] = time.perf_counter() - (start + arr[i])
-                tickets[i] = srv.submit(*rows[i])
+            def feed():
+                for i in range(nq):
+                    d = start + arr[i] - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    lag[i] = time.perf_counter() - (start + arr[i])
+                    tickets[i] = srv.submit(*batch[i])
 
-        th = threading.Thread(target=feed)
-        th.start()
-        th.join()
-        lat = np.empty(a.serve_queries)
-        for i in range(a.serve_queries):
-            lat[i] = srv.wait(tickets[i])[2] + lag[i]
-        span = time.perf_counter() - start
+            th = threading.Thread(target=feed)
+            th.start()
+            th.join()
+            lat = np.empty(nq)
+            for i in range(nq):
+                lat[i] = srv.wait(tickets[i])[2] + lag[i]
+            span = time.perf_counter() - start
+            rec = {"offered_qps": rate, "queries": nq, "achieved_qps": nq / span,
+                   "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+            rec["saturated"] = rec["achieved_qps"] < 0.9 * rate
+            sweep.append(rec)
+            print(f"[bench] serving {prec} {rate:g} qps: {rec}", file=sys.stderr, flush=True)
+            if rec["saturated"]:
+                break
         srv.stop()
-        res[prec] = {"path": ("bf16 keys, 2 graph-captured lanes, continuous admission" if graph else
-                              "float32 keys, 1 lane, per-batch launches, static FIFO batches"),
-                     "offered_qps": rate, "queries": a.serve_queries,
-                     "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                     "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                     "achieved_qps": a.serve_queries / span,
-                     "saturation_qps": sat_qps,
-                     "saturation_distances_per_s": sat_qps * n}
-        print(f"[bench] serving {prec}: {res[prec]}", file=sys.stderr, flush=True)
-    res["setup"] = (f"Poisson arrivals at {a.serve_rate:g} qps, 10-500 words per query, up to "
-                    f"{a.serve_slots} queries per batch; saturation = {a.serve_sat} queries submitted at once")
-    return res
+        out[prec] = {"path": ("bf16 keys, continuous batching: queries join free slots of running batches, "
+                              "graph-captured batches" if graph else
+                              "float32 keys, plain FIFO batches launched one at a time"),
+                     "saturation_qps": sat_qps, "saturation_distances_per_s": sat_qps * n, "sweep": sweep}
+    return out
+
+
+def run_batch(ctx, q, out, a, precision, steps, warmup):
+    """Warm-up and timed whole-batch steps of one precision: (s per step,
+    per-phase record summed over the timed steps)."""
+    import torch
+
+    def step():
+        ctx.topl(*q, a.ell, method=a.method, k=a.k, direction=a.direction, precision=precision, out=out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    phases = {}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        for p in ctx.profile_get():
+            d = phases.setdefault(p["name"], {"ms": 0.0, "launches": 0, "work": 0.0})
+            d["ms"] += p["ms"]
+            d["launches"] += p["launches"]
+            d["work"] += p["work"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ctx.profile(False)
+    return dt, phases
+
+
+def phase_report(phases, steps):
+    rep = {}
+    for k, v in phases.items():
+        r = {"ms_per_step": v["ms"] / steps, "launches_per_step": v["launches"] / steps}
+        if k == "phase1_table" and v["ms"] > 0:
+            r["algorithmic_TFLOPs"] = v["work"] / (v["ms"] * 1e-3) / 1e12
+        if k == "phase2" and v["ms"] > 0:
+            # A2 model: every query streams the database and reads its tables once
+            r["algorithmic_GBps_A2"] = v["work"] / (v["ms"] * 1e-3) / 1e9
+        rep[k] = r
+    return rep
+
+
+def roofline_of(phases, precision, a):
+    """Roofline of the dominant kernel: the phase-1 table pass (MFMA-bound,
+    algorithmic flops 2 v_used H m per launch against the key precision's
+    dense peak) or phase 2 (A2 bytes per launch against HBM)."""
+    p1 = phases.get("phase1_table", {"ms": 0.0, "launches": 1, "work": 0.0})
+    p2 = phases.get("phase2", {"ms": 0.0, "launches": 1, "work": 0.0})
+    if p1["ms"] >= p2["ms"]:
+        ms = p1["ms"] / max(1, p1["launches"])
+        flops = p1["work"] / max(1, p1["launches"])
+        ach = flops / (ms * 1e-3) if ms > 0 else 0.0
+        peak = PEAKS.get(precision, PEAKS["fp32"])
+        kernel = "k_phase1_bf16" if precision == "bf16" else phase1_kernel(a.method, a.k, precision, 300)
+        return {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": measured_traffic(kernel, a, precision), "kernel": kernel, "avg_launch_ms": ms,
+                "flops_per_launch": flops}
+    ms = p2["ms"] / max(1, p2["launches"])
+    byt = p2["work"] / max(1, p2["launches"])
+    ach = byt / (ms * 1e-3) if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": ach / HBM_PEAK,
+            "traffic": measured_traffic("k_phase2_persistent", a, precision), "kernel": "k_phase2_persistent",
+            "avg_launch_ms": ms, "bytes_per_launch": byt}
 
 
 def main():
@@ -469,9 +565,7 @@ def main():
         copy_calibration()
         return
     import numpy as np
-    import torch
 
-    from paper_1812_02091_amd import lcemd
     from synth import make_workload
 
     kw = {}
@@ -479,106 +573,81 @@ def main():
         kw["n"] = a.n
     if a.B:
         kw["B"] = a.B
+    t0 = time.time()
     w = make_workload(a.workload, **kw)
-    dev = torch.device("cuda:0")
-    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0)
-    qp, qc, qv = [torch.from_numpy(x).to(dev) for x in (w.queries.rowptr, w.queries.col, w.queries.val)]
-    idx = torch.empty((w.queries.n, a.ell), dtype=torch.int64, device=dev)
-    dist = torch.empty((w.queries.n, a.ell), dtype=torch.float32, device=dev)
-
-    def step():
-        ctx.topl(qp, qc, qv, a.ell, method=a.method, k=a.k, direction=a.direction,
-                 precision=a.precision, out=(idx, dist))
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    phases = {}
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-        for p in ctx.profile_get():
-            d = phases.setdefault(p["name"], {"ms": 0.0, "launches": 0, "work": 0.0})
-            d["ms"] += p["ms"]
-            d["launches"] += p["launches"]
-            d["work"] += p["work"]
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / a.steps
-    ctx.profile(False)
-    B, n = w.queries.n, w.db.n
-    value = B * n / dt
-
-    # roofline of the dominant kernel: phase-1 distance contraction (MFMA)
-    p1 = phases.get("phase1_table", {"ms": 0.0, "launches": 1, "work": 0.0})
-    per_launch_ms = p1["ms"] / max(1, p1["launches"])
-    per_launch_flops = p1["work"] / max(1, p1["launches"])
-    achieved = per_launch_flops / (per_launch_ms * 1e-3) if per_launch_ms > 0 else 0.0
-    peak = PEAKS.get(a.precision, PEAKS["fp32"])
-    kernel = phase1_kernel(a.method, a.k, a.precision, w.V.shape[1])
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": measured_traffic(kernel, a),
-                "kernel": kernel,
-                "avg_launch_ms": per_launch_ms,
-                "flops_per_launch": per_launch_flops}
-    p2 = phases.get("phase2")
-    phase_report = {k: {"ms_per_step": v["ms"] / a.steps, "launches_per_step": v["launches"] / a.steps}
-                    for k, v in phases.items()}
-    if p2:
-        p2_ms = p2["ms"] / max(1, p2["launches"])
-        p2_bytes = p2["work"] / max(1, p2["launches"])
-        phase_report["phase2"]["algorithmic_GBps"] = p2_bytes / (p2_ms * 1e-3) / 1e9
-        phase_report["phase2"]["hbm_frac"] = p2_bytes / (p2_ms * 1e-3) / HBM_PEAK
-
-    cpu, orows = None, None
+    print(f"[bench] {a.workload} workload built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    # the CPU baseline runs first, in forked workers, before any GPU work
+    full = a.workload == "text-1M" and not kw
+    cpu, orow = (None, None)
     if not a.no_cpu:
-        cpu, orows = cpu_baseline(w, a.method, a.k, a.ell, min(a.cpu_queries, B))
+        cpu, orow = cpu_baseline(a.cpu_workers, a.method, a.k, w if full else make_workload("text-1M"))
+        print(f"[bench] oracle baseline: {cpu['value']:.0f} distances/s on {cpu['cores']} workers",
+              file=sys.stderr, flush=True)
+        if not full:
+            orow = None
 
-    # the other phase-1 arithmetics on the same batch, against this run's
-    # path (top-l agreement) and against the float64 oracle (sampled rows)
-    precisions = {}
-    if orows is not None:
-        precisions[a.precision] = oracle_error(ctx, w, len(orows), orows, a.method, a.k, a.precision)
+    import torch
+
+    from paper_1812_02091_amd import lcemd
+
+    dev = torch.device("cuda:0")
+    ctx = lcemd.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, device=0, precisions=("bf16", "fp8"))
+    q = [torch.from_numpy(x).to(dev) for x in (w.queries.rowptr, w.queries.col, w.queries.val)]
+    B, n = w.queries.n, w.db.n
+    out = (torch.empty((B, a.ell), dtype=torch.int64, device=dev), torch.empty((B, a.ell), dtype=torch.float32, device=dev))
+
+    dt, phases = run_batch(ctx, q, out, a, a.precision, a.steps, a.warmup)
+    value = B * n / dt
+    print(f"[bench] {a.precision}: {dt:.3f} s per step", file=sys.stderr, flush=True)
+    roofline = roofline_of(phases, a.precision, a)
+    ref_idx, ref_dist = out[0].cpu().numpy(), out[1].cpu().numpy()
+    rng = np.random.default_rng(77)
+    picks = [(int(b), int(j)) for b, j in zip(rng.integers(0, B, 24), rng.integers(0, a.ell, 24))]
+    precisions = {a.precision: {"distances_per_s": value, "s_per_step": dt, "phases": phase_report(phases, a.steps)}}
+    precisions[a.precision].update(oracle_pairs_error(w, ref_idx, ref_dist, picks, a.method, a.k))
+    results = {a.precision: (ref_idx, ref_dist)}
     if not a.no_compare:
-        ref_idx = idx.cpu().numpy()
-        ref_dist = dist.cpu().numpy().astype(np.float64)
         for other in ("fp32", "bf16", "fp8"):
             if other == a.precision:
                 continue
-            oi = torch.empty_like(idx)
-            od = torch.empty_like(dist)
-
-            def ostep():
-                ctx.topl(qp, qc, qv, a.ell, method=a.method, k=a.k, direction=a.direction,
-                         precision=other, out=(oi, od))
-
-            ostep()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(max(1, a.steps // 2)):
-                ostep()
-            torch.cuda.synchronize()
-            odt = (time.perf_counter() - t1) / max(1, a.steps // 2)
-            oidx = oi.cpu().numpy()
-            agree = float(np.mean([len(set(ref_idx[i]) & set(oidx[i])) / a.ell for i in range(B)]))
-            maxrel = float(np.max(np.abs(od.cpu().numpy().astype(np.float64) - ref_dist)
-                                  / np.maximum(ref_dist, 1e-30)))
-            rec = {"value": B * n / odt, "ms_per_step": odt * 1e3,
-                   f"top{a.ell}_agreement_vs_{a.precision}": agree,
-                   f"max_rel_diff_of_returned_distances_vs_{a.precision}": maxrel}
-            if orows is not None:
-                rec.update(oracle_error(ctx, w, len(orows), orows, a.method, a.k, other))
+            odt, oph = run_batch(ctx, q, out, a, other, a.other_steps, 1)
+            oi, od = out[0].cpu().numpy(), out[1].cpu().numpy()
+            results[other] = (oi, od)
+            rec = {"distances_per_s": B * n / odt, "s_per_step": odt, "phases": phase_report(oph, a.other_steps),
+                   "roofline_of_dominant_kernel": roofline_of(oph, other, a)}
+            rec.update(oracle_pairs_error(w, oi, od, picks, a.method, a.k))
             precisions[other] = rec
+            print(f"[bench] {other}: {odt:.3f} s per step", file=sys.stderr, flush=True)
+        if "fp32" in results:
+            fi = results["fp32"][0]
+            for p, (ii, _) in results.items():
+                if p != "fp32":
+                    precisions[p][f"top{a.ell}_agreement_vs_fp32"] = float(
+                        np.mean([len(set(fi[i]) & set(ii[i])) / a.ell for i in range(B)]))
+    if orow is not None:
+        # the whole oracle row of query 0 (all 1M documents): the GPU's
+        # symmetric distances of the same query, and its top-l list against
+        # the oracle's
+        sub_q = w.queries.take([0])
+        g = ctx.distances(sub_q.rowptr, sub_q.col, sub_q.val, method=a.method, k=a.k, direction="sym",
+                          precision=a.precision)[0].astype(np.float64)
+        rel = np.abs(g - orow) / np.maximum(np.abs(orow), 1e-30)
+        o_top = np.lexsort((np.arange(orow.shape[0]), orow))[:a.ell]
+        precisions[a.precision].update({"oracle_row_max_rel_err": float(rel.max()),
+                                        "oracle_row_pairs": int(rel.size),
+                                        "oracle_row_topl_overlap": len(set(o_top.tolist()) &
+                                                                       set(ref_idx[0].tolist())) / a.ell})
     fb, fixed = ctx.counters()
     counters = {"fallback_tiles": fb, "rows_redone_exactly": fixed}
+    serving = None if a.no_serving else serve_sweep(a, lcemd, ctx, w.V.shape[0], n)
     ctx.close()
+    del q, out
     image = None if a.no_big else image_section(a, lcemd)
     selfjoin = None if a.no_big else selfjoin_section(a, lcemd)
-    measures = None if a.no_big else measures_section(a, lcemd)
-    dense = None if a.no_big else dense_section(a, lcemd)
-    big = None if a.no_big else big_workload(a, lcemd)
+    measures = measures_section(a, lcemd) if a.all_sections else None
+    dense = dense_section(a, lcemd) if a.all_sections else None
 
-    out = {
+    res = {
         "metric": "query-doc ACT distances/sec + p50/p99 query latency, BF16 vs FP32 path",
         "value": value,
         "unit": "distances/s",
@@ -593,21 +662,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: vocab {w.V.shape[0]} x {w.V.shape[1]}, {n} database "
                                f"histograms ({w.db.nnz} non-zeros), {B} queries, "
-                               f"{a.method.upper()} k={a.k} {a.direction}, top-{a.ell}",
+                               f"{a.method.upper()} k={a.k} {a.direction}, top-{a.ell}, {a.precision} phase-1 keys",
                    "global_batch": B, "database": n, "k": a.k, "ell": a.ell,
                    "method": a.method, "direction": a.direction, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "phases": phase_report,
+        "phases": precisions[a.precision]["phases"],
         "precisions": precisions,
         "counters": counters,
+        "serving": serving,
         "image": image,
         "selfjoin": selfjoin,
         "measures": measures,
         "image_bg": dense,
-        "text_1M": big,
     }
-    print(json.dumps(out))
+    print(json.dumps(res))
 
 
 if __name__ == "__main__":

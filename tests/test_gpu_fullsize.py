@@ -152,10 +152,10 @@ def certified_row(orc, qc, qw, method, k, tau, tol_frac=1e-5):
 
 def test_text_1m_whole_rows(L):
     """1M-word vocabulary, 1M documents, ACT k=8 symmetric top-16 (the
-    precision workload's shape): for two queries the float32 and bf16 lists
-    against whole oracle rows, certified by RWMD lower bounds -- the oracle
-    evaluates exactly every document that could enter the top-16, and no
-    other document can."""
+    precision workload's shape): for one query the float32 and bf16 lists
+    against its whole oracle row, certified by RWMD lower bounds -- the
+    oracle evaluates exactly every document that could enter the top-16,
+    and no other document can."""
     import torch
 
     w = make_workload("text-1M", B=16)
@@ -167,13 +167,15 @@ def test_text_1m_whole_rows(L):
     ib, db = ib.cpu().numpy(), db.cpu().numpy()
     ctx.close()
     orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
-    swaps = 0
-    for b in (3, 11):
-        qc, qw = w.queries.row(b)
-        tau = float(max(dist[b, -1], db[b, -1]))
-        row, exact = certified_row(orc, qc, qw, "act", 8, tau)
-        say(f"  query {b} ({qc.size} words): {int(exact.sum())} documents evaluated exactly")
-        assert exact[idx[b]].all() and exact[ib[b]].all()
-        swaps += P.check_topl(idx[b], dist[b], row, 16, f"query {b} fp32")
-        swaps += P.check_topl(ib[b], db[b], row, 16, f"query {b} bf16")
+    # the shortest of the 16 queries keeps the oracle's vocabulary block
+    # (every used word against the query's words) to a few seconds
+    b = int(np.argmin(np.diff(w.queries.rowptr)))
+    qc, qw = w.queries.row(b)
+    tau = float(max(dist[b, -1], db[b, -1]))
+    say(f"[gpu] 1M-word whole row: oracle certificate for query {b} ({qc.size} words)")
+    row, exact = certified_row(orc, qc, qw, "act", 8, tau)
+    say(f"  query {b}: {int(exact.sum())} documents evaluated exactly")
+    assert exact[idx[b]].all() and exact[ib[b]].all()
+    swaps = P.check_topl(idx[b], dist[b], row, 16, f"query {b} fp32")
+    swaps += P.check_topl(ib[b], db[b], row, 16, f"query {b} bf16")
     assert swaps <= 2, swaps
