@@ -188,6 +188,24 @@ int lcemd_distances(lcemd_ctx* ctx, const lcemd_query* q, const lcemd_opts* o,
 int lcemd_topl(lcemd_ctx* ctx, const lcemd_query* q, const lcemd_opts* o,
                int32_t l, int64_t* idx, float* dist);
 
+/* lcemd_topl for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * top-l, but every buffer of the call (tables, the D2Q distance rows,
+ * candidate lists, counters) comes from a fixed 256 MiB device region that
+ * the library holds per GPU from its first use there to process end; the
+ * call itself allocates nothing, host or device.  Restrictions:
+ * LCEMD_PTR_DEVICE (queries and outputs in device memory), direction D2Q,
+ * 1..4096 queries of at most 512 words, B x n distances within half the
+ * region (LCEMD_E_CAPACITY otherwise, or when the tables of one query do not
+ * fit what is left); bf16 / fp8 keys need their copy built at load
+ * (LCEMD_MAKE_BF16 / LCEMD_MAKE_FP8), else LCEMD_E_UNSUPPORTED.  Results
+ * equal lcemd_topl's (same kernels).  Every call on a GPU shares that GPU's
+ * region and leaves its contents behind (what must start at zero is cleared
+ * by each call): calls that overlap on one GPU -- from several contexts or
+ * threads -- race and must be serialised by the caller. */
+int lcemd_topl_noalloc(lcemd_ctx* ctx, const lcemd_query* q, const lcemd_opts* o, int32_t l,
+                       int64_t* idx, float* dist);
+
 /* Phase-1 tables of Sec. 4 for every query and every used vocabulary word
  * (used words in ascending word id order; lcemd_used_vocab lists them):
  * S = positions (0-based, within the query row) of the k_eff = min(k, h_b)

@@ -25,6 +25,23 @@ thread_local std::string g_create_error;
 
 namespace lcemd_host {
 
+int arena_get(lcemd_ctx* c, const char* name, size_t bytes, void** out) {
+  Arena& A = c->arena;
+  for (int i = 0; i < A.nslot; ++i)
+    if (strcmp(A.slot[i].name, name) == 0 && A.slot[i].bytes >= bytes) {
+      *out = A.base + A.slot[i].off;
+      return LCEMD_OK;
+    }
+  const size_t off = (A.used + 255) / 256 * 256;
+  if (A.nslot >= 32 || off + bytes > A.cap)
+    return fail(c, LCEMD_E_CAPACITY, "the call needs more than the %zu bytes of the allocation-free scratch (%s: %zu bytes)",
+                A.cap, name, bytes);
+  A.slot[A.nslot++] = Arena::Slot{name, off, bytes};
+  A.used = off + bytes;
+  *out = A.base + off;
+  return LCEMD_OK;
+}
+
 int fail(lcemd_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -177,7 +194,7 @@ int stage_query(lcemd_ctx* c, const lcemd_query* q, QDev& Q) {
   if (q->B > (int64_t(1) << 24)) return fail(c, LCEMD_E_CAPACITY, "query batch too large");
   Q.B = q->B;
   Q.device = (q->flags & LCEMD_PTR_DEVICE) != 0;
-  Q.hptr.resize(Q.B + 1);
+  if (!c->arena.base) Q.hptr.resize(Q.B + 1);
   if (!Q.device) {
     memcpy(Q.hptr.data(), q->rowptr, sizeof(int64_t) * (Q.B + 1));
     int rc = check_csr_host(c, "query", q->rowptr, q->col, q->val, Q.B, c->v, true, &Q.hmax);
@@ -196,22 +213,33 @@ int stage_query(lcemd_ctx* c, const lcemd_query* q, QDev& Q) {
     Q.col = dc;
     Q.val = dv;
   } else {
-    HIPCHK(c, hipMemcpyAsync(Q.hptr.data(), q->rowptr, sizeof(int64_t) * (Q.B + 1), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    int rc = check_ptr_host(c, "query", Q.hptr.data(), Q.B, &Q.hmax);
-    if (rc) return rc;
-    Q.nnz = Q.hptr[Q.B];
+    int rc;
     int* derr;
-    if ((rc = wsget(c, "q_err", 1, derr))) return rc;
-    HIPCHK(c, hipMemsetAsync(derr, 0, sizeof(int), c->stream));
+    if ((rc = wsget(c, "q_err", 2, derr))) return rc;
+    HIPCHK(c, launch_zero_ints(derr, 2, c->stream));
+    if (c->arena.base) {
+      // allocation-free: row pointers checked on the device too (no host
+      // copy of them); the total and the longest row come back as numbers
+      HIPCHK(c, hipMemcpyAsync(&Q.nnz, q->rowptr + Q.B, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    } else {
+      HIPCHK(c, hipMemcpyAsync(Q.hptr.data(), q->rowptr, sizeof(int64_t) * (Q.B + 1), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if ((rc = check_ptr_host(c, "query", Q.hptr.data(), Q.B, &Q.hmax))) return rc;
+      Q.nnz = Q.hptr[Q.B];
+    }
     HIPCHK(c, launch_validate_csr(q->rowptr, q->col, q->val, Q.B, c->v, 1, derr, c->stream));
-    int herr = 0;
-    HIPCHK(c, hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    int herr[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(herr, derr, sizeof(int) * 2, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (herr & 2) return fail(c, LCEMD_E_BAD_CSR, "query: column ids must be strictly increasing in [0, %lld)", (long long)c->v);
-    if (herr & 4) return fail(c, LCEMD_E_BAD_CSR, "query: weights must be finite and > 0");
-    if (herr & 8) return fail(c, LCEMD_E_BAD_CSR, "query: a row does not sum to 1");
-    if (herr) return fail(c, LCEMD_E_BAD_CSR, "query: malformed CSR");
+    if (c->arena.base) {
+      if (herr[0] & 1) return fail(c, LCEMD_E_BAD_CSR, "query: malformed row pointers (empty, decreasing or over %d words)", LCEMD_MAX_HIST);
+      Q.hmax = herr[1];
+    }
+    const int herr0 = herr[0];
+    if (herr0 & 2) return fail(c, LCEMD_E_BAD_CSR, "query: column ids must be strictly increasing in [0, %lld)", (long long)c->v);
+    if (herr0 & 4) return fail(c, LCEMD_E_BAD_CSR, "query: weights must be finite and > 0");
+    if (herr0 & 8) return fail(c, LCEMD_E_BAD_CSR, "query: a row does not sum to 1");
+    if (herr0) return fail(c, LCEMD_E_BAD_CSR, "query: malformed CSR");
     Q.ptr = q->rowptr;
     Q.col = q->col;
     Q.val = q->val;
@@ -233,6 +261,8 @@ int check_opts(lcemd_ctx* c, const lcemd_opts* o) {
 
 constexpr int kMargin = 8;  // over-selection for approximate (bf16/fp8) keys
 constexpr int kFixCap = 1 << 23;  // rows per launch that may be redone exactly (64 MB list)
+constexpr int kFixCapNoAlloc = 1 << 16;  // the same in allocation-free calls
+constexpr int kNoAllocMaxQueries = 4096;   // queries per allocation-free call
 
 int pow2ceil(int x) {
   int p = 2;
@@ -424,12 +454,15 @@ int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, 
   if ((rc = wsget(c, "ovf", 1, ovf))) return rc;
   int64_t q0 = 0;
   while (q0 < Q.B) {
-    int64_t Bt = (int64_t)std::max<size_t>(1, c->table_budget / (per_q * 2 * zw_pairs(KT)));
+    // tables: under the context's budget, or (allocation-free) half of what
+    // the scratch region has left
+    const size_t tbudget = c->arena.base ? (c->arena.cap - std::min(c->arena.cap, c->arena.used)) / 2 : c->table_budget;
+    int64_t Bt = (int64_t)std::max<size_t>(1, tbudget / (per_q * 2 * zw_pairs(KT)));
     Bt = std::min<int64_t>(Bt, 16384);  // also bounds the rows a tile may need to redo
     const int64_t nq = std::min<int64_t>(Bt, Q.B - q0);
     float2* ZW;
     if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * db.v_used * 2 * zw_pairs(KT), ZW))) return rc;
-    HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
+    HIPCHK(c, launch_zero_ints(ovf, 1, c->stream));
     P1Args a = base_args(c, db, Q, o);
     a.qnnz = Q.nnz;
     a.KT = KT;
@@ -441,11 +474,12 @@ int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, 
     // rows whose quantised selection is not certified are listed for an
     // exact redo (every precision on the 128-row kernel)
     int* fixc = nullptr;
-    if ((rc = wsget(c, "fix_count", 1, fixc)) || (rc = wsget(c, "fix_list", kFixCap, a.fix_list))) return rc;
-    HIPCHK(c, hipMemsetAsync(fixc, 0, sizeof(int), c->stream));
+    const int fixcap = c->arena.base ? kFixCapNoAlloc : kFixCap;
+    if ((rc = wsget(c, "fix_count", 1, fixc)) || (rc = wsget(c, "fix_list", fixcap, a.fix_list))) return rc;
+    HIPCHK(c, launch_zero_ints(fixc, 1, c->stream));
     a.fix_count = fixc;
-    a.fix_cap = kFixCap;
-    int64_t H = Q.hptr[q0 + nq] - Q.hptr[q0];
+    a.fix_cap = fixcap;
+    const int64_t H = Q.hptr.empty() ? Q.nnz : Q.hptr[q0 + nq] - Q.hptr[q0];
     if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)db.v_used * (double)H * (double)c->m))) return rc;
     const int list_depth = full_lists ? KT : std::min(KT, kIctList);
     if ((rc = p1_launch(c, a, P1_TABLE, prec, list_depth, Q.hmax, Q.hmax))) return rc;
@@ -518,7 +552,7 @@ int run_pairs(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, P1Args a, float*
   a.partial = partial;
   a.overflow = ovf;
   const int depth = table_depth(o, c->db_hmax);
-  HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
+  HIPCHK(c, launch_zero_ints(ovf, 1, c->stream));
   if ((rc = prof_begin(c, "phase1_pair_q2d", (double)a.npairs))) return rc;
   if ((rc = p1_launch(c, a, P1_PAIR, o->precision, depth, c->db_hmax, Q.hmax))) return rc;
   if ((rc = prof_end(c))) return rc;
@@ -668,6 +702,9 @@ int lcemd_create(lcemd_ctx** out, int device) {
     return LCEMD_E_HIP;
   }
   c->stream = c->own_stream;
+  // the allocation-free scratch region of this device (looked up once per
+  // device, with the device current); a failure only disables that call
+  c->scratch_rc = noalloc_setup(device, &c->scratch);
   if (const char* fk = getenv("LCEMD_FORCE_KERNEL")) c->force_kernel = atoi(fk);
   if (const char* sc = getenv("LCEMD_SYM_CANDIDATES")) c->sym_candidates = atoi(sc);
   *out = c;
@@ -1029,6 +1066,67 @@ int lcemd_topl(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t 
   return finish_call(c);
 }
 
+// lcemd_topl for callers that cannot allocate: every buffer of the call is
+// carved from this device's scratch region (noalloc.hip), which the arena
+// hands out for the call and reclaims when it returns.
+int lcemd_topl_noalloc(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t l, int64_t* idx,
+                       float* dist) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  c->err.clear();
+  if ((rc = check_opts(c, o))) return rc;
+  if (!q || !(q->flags & LCEMD_PTR_DEVICE))
+    return fail(c, LCEMD_E_INVALID_ARG, "allocation-free top-l: queries and outputs must be device pointers");
+  if (!idx || !dist) return fail(c, LCEMD_E_INVALID_ARG, "idx/dist must not be NULL");
+  if (o->direction != LCEMD_D2Q) return fail(c, LCEMD_E_UNSUPPORTED, "allocation-free top-l: direction D2Q only");
+  if ((o->precision == LCEMD_BF16 && !c->Vb) || (o->precision == LCEMD_FP8 && !c->V8))
+    return fail(c, LCEMD_E_UNSUPPORTED,
+                "allocation-free top-l: load the embeddings with LCEMD_MAKE_BF16 / LCEMD_MAKE_FP8 for that precision");
+  if (!c->scratch) return fail(c, LCEMD_E_HIP, "no allocation-free scratch on this device (lookup failed: %d)", c->scratch_rc);
+  const int64_t n = c->n;
+  const int64_t avail = n - (o->exclude_self >= 0 ? 1 : 0);
+  if (l < 1 || l > LCEMD_MAX_L || l > avail)
+    return fail(c, LCEMD_E_INVALID_ARG, "need 1 <= l <= min(%d, %lld)", LCEMD_MAX_L, (long long)avail);
+  if (q->B < 1 || q->B > kNoAllocMaxQueries)
+    return fail(c, LCEMD_E_CAPACITY, "allocation-free top-l: 1..%d queries per call", kNoAllocMaxQueries);
+  const double need = (double)q->B * (double)n * 4.0 + (double)q->B * l * 8.0;
+  if (need > (double)noalloc_capacity() / 2)
+    return fail(c, LCEMD_E_CAPACITY,
+                "allocation-free top-l: %lld queries x %lld rows need %.0f bytes of distances, over half of the %zu-byte scratch",
+                (long long)q->B, (long long)n, need, noalloc_capacity());
+  (void)hipSetDevice(c->device);
+  // the arena for this call; profiling (events) stays off
+  struct Guard {
+    lcemd_ctx* c;
+    bool prof;
+    Guard(lcemd_ctx* c_) : c(c_), prof(c_->prof) {
+      c->arena = Arena();
+      c->arena.base = static_cast<char*>(c->scratch);
+      c->arena.cap = noalloc_capacity();
+      c->prof = false;
+    }
+    ~Guard() {
+      c->arena = Arena();
+      c->prof = prof;
+    }
+  } guard(c);
+  prof_reset(c);
+  QDev Q;
+  if ((rc = stage_query(c, q, Q))) return rc;
+  if (Q.hmax > kSegShort)
+    return fail(c, LCEMD_E_CAPACITY, "allocation-free top-l: queries of at most %d words", kSegShort);
+  const int64_t excl = o->exclude_self >= 0 ? o->exclude_self : -1;
+  if (excl >= 0 && excl + Q.B > n) return fail(c, LCEMD_E_INVALID_ARG, "exclude_self + B exceeds the database size");
+  float* d2q;
+  uint64_t* cand;
+  if ((rc = wsget(c, "d2q_full", (size_t)Q.B * n, d2q)) || (rc = wsget(c, "cand", (size_t)Q.B * l, cand))) return rc;
+  if ((rc = run_d2q(c, Q, o, d2q, n))) return rc;
+  if ((rc = select_rows(c, d2q, n, n, Q.B, l, nullptr, excl, cand))) return rc;
+  HIPCHK(c, launch_unpack_topl(cand, l, Q.B, nullptr, l, idx, dist, c->stream));
+  HIPCHK(c, hipGetLastError());
+  return LCEMD_OK;
+}
+
 int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_t* S, float* Z,
                  float* W) {
   int rc = check_ready(c);
@@ -1066,8 +1164,8 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
   if ((rc = wsget(c, "ovf", 1, ovf)) || (rc = wsget(c, "fix_count", 1, fixc)) ||
       (rc = wsget(c, "fix_list", kFixCap, a.fix_list)))
     return rc;
-  HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
-  HIPCHK(c, hipMemsetAsync(fixc, 0, sizeof(int), c->stream));
+  HIPCHK(c, launch_zero_ints(ovf, 1, c->stream));
+  HIPCHK(c, launch_zero_ints(fixc, 1, c->stream));
   a.overflow = ovf;
   a.fix_count = fixc;
   a.fix_cap = kFixCap;
@@ -1081,8 +1179,8 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
       // redo everything with float32 keys: rows listed for an exact redo by
       // the first launch are dropped (the rerun lists its own), and an
       // overflow of the rerun itself is an error
-      HIPCHK(c, hipMemsetAsync(ovf, 0, sizeof(int), c->stream));
-      HIPCHK(c, hipMemsetAsync(fixc, 0, sizeof(int), c->stream));
+      HIPCHK(c, launch_zero_ints(ovf, 1, c->stream));
+      HIPCHK(c, launch_zero_ints(fixc, 1, c->stream));
       if ((rc = p1_launch(c, a, P1_TABLE_FULL, LCEMD_FP32, o->k, Q.hmax, Q.hmax))) return rc;
       ++c->fallbacks;
       HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));

@@ -22,6 +22,18 @@ struct ProfRec {
   double work;
 };
 
+// A call's buffers carved from a fixed device region instead of allocated
+// (lcemd_topl_noalloc): fixed slots, no host or device allocation.
+struct Arena {
+  char* base = nullptr;  // null: scratch is allocated (grow-only, see wsget)
+  size_t cap = 0, used = 0;
+  struct Slot {
+    const char* name;
+    size_t off, bytes;
+  } slot[32];
+  int nslot = 0;
+};
+
 struct lcemd_ctx {
   int device = 0;
   hipStream_t own_stream = nullptr;
@@ -57,6 +69,10 @@ struct lcemd_ctx {
   int sym_candidates = 0; // test hook (LCEMD_SYM_CANDIDATES): first candidate count of the SYM top-l
   int64_t fallbacks = 0;  // tiles redone with float32 keys / deeper lists
   int64_t fixed_rows = 0; // bf16 table rows redone exactly one by one
+  // allocation-free calls: this device's scratch region and the arena over it
+  void* scratch = nullptr;
+  int scratch_rc = 0;
+  Arena arena;
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
@@ -71,6 +87,9 @@ int check_csr_host(lcemd_ctx* c, const char* what, const int64_t* ptr, const int
 int ensure_precision(lcemd_ctx* c, int prec);
 int p1_launch(lcemd_ctx* c, lcemd::P1Args& a, int mode, int prec, int depth, int seg_hmax,
               int row_hmax);
+// this device's allocation-free scratch region (found once per device)
+int noalloc_setup(int device, void** out);
+size_t noalloc_capacity();
 int pow2ceil(int x);
 
 #define HIPCHK(ctx, expr)                                                                  \
@@ -98,9 +117,17 @@ int dalloc(lcemd_ctx* c, T*& p, size_t count, const char* what) {
   return LCEMD_OK;
 }
 
-// grow-only named scratch buffer
+int arena_get(lcemd_ctx* c, const char* name, size_t bytes, void** out);
+
+// grow-only named scratch buffer (carved from the arena while one is set)
 template <typename T>
 int wsget(lcemd_ctx* c, const char* name, size_t count, T*& out) {
+  if (c->arena.base) {
+    void* p = nullptr;
+    const int rc = arena_get(c, name, std::max<size_t>(count, 1) * sizeof(T), &p);
+    out = static_cast<T*>(p);
+    return rc;
+  }
   DevBuf& b = c->ws[name];
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   if (b.bytes < bytes) {

@@ -210,8 +210,12 @@ struct OccEntry {
   int device;
   int per_cu;
 };
+// a fixed table (no allocation at launch time); once full, further
+// kernels are queried at every launch
+constexpr int kOccCap = 512;
 std::mutex g_occ_mu;
-std::vector<OccEntry> g_occ;
+OccEntry g_occ[kOccCap];
+int g_nocc = 0;
 int g_cus[64] = {0};
 }  // namespace
 
@@ -221,13 +225,13 @@ int persistent_grid(const void* fn, int threads, size_t shmem, int64_t items) {
   int per_cu = -1;
   {
     std::lock_guard<std::mutex> g(g_occ_mu);
-    for (const OccEntry& e : g_occ)
-      if (e.fn == fn && e.shmem == shmem && e.device == dev) per_cu = e.per_cu;
+    for (int i = 0; i < g_nocc; ++i)
+      if (g_occ[i].fn == fn && g_occ[i].shmem == shmem && g_occ[i].device == dev) per_cu = g_occ[i].per_cu;
     if (!g_cus[dev] && hipDeviceGetAttribute(&g_cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return -1;
     if (per_cu < 0) {
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shmem) != hipSuccess) return -1;
-      g_occ.push_back({fn, shmem, dev, per_cu});
+      if (g_nocc < kOccCap) g_occ[g_nocc++] = OccEntry{fn, shmem, dev, per_cu};
     }
   }
   if (per_cu < 1) return -1;

@@ -147,8 +147,9 @@ hipError_t launch_make_fp8(const float* V, int64_t v, int m_pad, int m8, uint8_t
 }
 
 // Validation of a CSR histogram batch resident on the device; each failing
-// row sets a bit of *err: 1 = row pointers, 2 = column ids, 4 = weights,
-// 8 = row sum (only when normalised rows are required).
+// row sets a bit of err[0]: 1 = row pointers, 2 = column ids, 4 = weights,
+// 8 = row sum (only when normalised rows are required); err[1] gets the
+// longest row (both start at 0).
 __global__ __launch_bounds__(kThreads) void k_validate_csr(const int64_t* __restrict__ ptr,
                                                            const int32_t* __restrict__ col,
                                                            const float* __restrict__ val,
@@ -158,7 +159,8 @@ __global__ __launch_bounds__(kThreads) void k_validate_csr(const int64_t* __rest
   if (r >= rows) return;
   const int64_t a = ptr[r], b = ptr[r + 1];
   int e = 0;
-  if (b <= a || b - a > LCEMD_MAX_HIST || a < 0) e |= 1;
+  if (b <= a || b - a > LCEMD_MAX_HIST || a < 0 || (r == 0 && a != 0)) e |= 1;
+  else atomicMax(err + 1, (int)(b - a));
   if (!(e & 1)) {
     double sum = 0.0;
     int prev = -1;

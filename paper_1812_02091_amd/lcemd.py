@@ -75,6 +75,8 @@ _SIGS = {
                              C.c_void_p, C.c_void_p]),
     "lcemd_tables": (C.c_int, [C.c_void_p, C.POINTER(lcemd_query), C.POINTER(lcemd_opts),
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lcemd_topl_noalloc": (C.c_int, [C.c_void_p, C.POINTER(lcemd_query), C.POINTER(lcemd_opts), C.c_int32,
+                                     C.c_void_p, C.c_void_p]),
     "lcemd_selfjoin_topl": (C.c_int, [C.c_void_p, C.POINTER(lcemd_opts), C.c_int32, C.c_uint32,
                                       C.c_void_p, C.c_void_p]),
     "lcemd_used_vocab": (C.c_int64, [C.c_void_p, C.c_void_p]),
@@ -281,6 +283,15 @@ class Context:
             pi, pd = out[0].ctypes.data, out[1].ctypes.data
         self._check(self.lib.lcemd_topl(self.h, C.byref(q), C.byref(o), int(l), C.c_void_p(pi),
                                         C.c_void_p(pd)))
+        return out
+
+    def topl_noalloc(self, qptr, qcol, qval, l, out, method="act", k=1, precision="fp32", exclude_self=-1):
+        """lcemd_topl_noalloc: D2Q top-l with device tensors only; `out` =
+        (idx int64, dist float32) device tensors of shape (B, l)."""
+        q, keep, dev = self._query(qptr, qcol, qval)  # the library refuses host arrays
+        o = _opts(method, k, "d2q", precision, exclude_self)
+        self._check(self.lib.lcemd_topl_noalloc(self.h, C.byref(q), C.byref(o), int(l),
+                                                C.c_void_p(out[0].data_ptr()), C.c_void_p(out[1].data_ptr())))
         return out
 
     def selfjoin_topl(self, l, method="act", k=1, direction="sym", precision="fp32", device=False,
