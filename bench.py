@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-big", action="store_true", help="skip the image and self-join sections")
     ap.add_argument("--all-sections", action="store_true", help="also the measure and dense-image sections")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (no batch steps)")
     ap.add_argument("--serve-rates", default="200,500,1000,2000,5000", help="offered loads, queries/s")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival span per rate")
     ap.add_argument("--serve-sat", type=int, default=512, help="queries in the saturation burst")
@@ -417,10 +418,12 @@ def serve_sweep(a, lcemd, ctx, v, n):
     """Serving on the resident 1M-word database: open-loop Poisson streams of
     10-500-word queries (ACT k=8, symmetric top-16), each offered rate for
     about --serve-seconds, rising until the path saturates (achieved rate
-    below 90 % of the offered one), plus a saturation burst.  Two paths:
-    bf16 keys with continuous batching (queries join free slots of running
-    batches; graph-captured) and float32 keys with plain FIFO batches
-    launched one at a time.  Latency = completion - scheduled arrival."""
+    below 90 % of the offered one), plus a saturation burst.  Three paths:
+    bf16 keys on four launch lanes (continuous batching: a free lane takes
+    the waiting queries at once, so up to four batches run side by side),
+    bf16 keys on one lane, and float32 keys on one lane -- precision and
+    lane policy each change alone between two of them.  Latency =
+    completion - scheduled arrival."""
     import threading
 
     import numpy as np
@@ -434,9 +437,10 @@ def serve_sweep(a, lcemd, ctx, v, n):
     out = {"setup": (f"Poisson arrivals, 10-500 words per query, up to {a.serve_slots} queries per batch; each "
                      f"rate offered for ~{a.serve_seconds:g} s (200-3,000 queries) until saturation; saturation = "
                      f"{a.serve_sat} queries submitted at once")}
-    for prec, graph in (("bf16", True), ("fp32", False)):
+    for name, prec, graph, lanes in (("bf16", "bf16", True, 4), ("bf16_1lane", "bf16", True, 1),
+                                     ("fp32", "fp32", False, 1)):
         srv = lcemd.Server(ctx, method="act", k=8, precision=prec, l=16, max_slots=a.serve_slots,
-                           memory_budget=a.serve_budget << 30, use_graph=graph)
+                           memory_budget=a.serve_budget << 30, use_graph=graph, lanes=lanes)
         cur = 0
 
         def take(m):
@@ -481,13 +485,14 @@ def serve_sweep(a, lcemd, ctx, v, n):
                    "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
             rec["saturated"] = rec["achieved_qps"] < 0.9 * rate
             sweep.append(rec)
-            print(f"[bench] serving {prec} {rate:g} qps: {rec}", file=sys.stderr, flush=True)
+            print(f"[bench] serving {name} {rate:g} qps: {rec}", file=sys.stderr, flush=True)
             if rec["saturated"]:
                 break
         srv.stop()
-        out[prec] = {"path": ("bf16 keys, continuous batching: queries join free slots of running batches, "
-                              "graph-captured batches" if graph else
-                              "float32 keys, plain FIFO batches launched one at a time"),
+        out[name] = {"path": (f"{prec} keys, {lanes} launch lane{'s' if lanes > 1 else ''} (a free lane takes the "
+                              f"waiting queries at once), {'graph-captured' if graph else 'eagerly launched'} "
+                              f"batches"),
+                     "lanes": lanes,
                      "saturation_qps": sat_qps, "saturation_distances_per_s": sat_qps * n, "sweep": sweep}
     return out
 
@@ -596,6 +601,10 @@ def main():
     B, n = w.queries.n, w.db.n
     out = (torch.empty((B, a.ell), dtype=torch.int64, device=dev), torch.empty((B, a.ell), dtype=torch.float32, device=dev))
 
+    if a.serve_only:
+        print(json.dumps({"serving": serve_sweep(a, lcemd, ctx, w.V.shape[0], n)}))
+        ctx.close()
+        return
     dt, phases = run_batch(ctx, q, out, a, a.precision, a.steps, a.warmup)
     value = B * n / dt
     print(f"[bench] {a.precision}: {dt:.3f} s per step", file=sys.stderr, flush=True)

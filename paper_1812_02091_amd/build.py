@@ -22,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
           "-Wno-unused-result", "-I" + os.path.join(os.path.dirname(PKG), "include")]
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["api.cpp", "server.cpp", "serve_sim.cpp", "prep.hip", "phase1.hip", "phase1_fast.hip", "phase1_wide.hip", "phase1_bf16.hip", "phase2.hip", "noalloc.hip", "select.hip"]
+SOURCES = ["api.cpp", "server.cpp", "serve_sim.cpp", "prep.hip", "phase1.hip", "phase1_fast.hip", "phase1_wide.hip", "phase1_bf16.hip", "phase2.hip", "noalloc.hip", "reverse.hip", "select.hip"]
 
 
 def _compile(src: str) -> str:

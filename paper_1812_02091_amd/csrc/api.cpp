@@ -459,6 +459,9 @@ int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, 
     const size_t tbudget = c->arena.base ? (c->arena.cap - std::min(c->arena.cap, c->arena.used)) / 2 : c->table_budget;
     int64_t Bt = (int64_t)std::max<size_t>(1, tbudget / (per_q * 2 * zw_pairs(KT)));
     Bt = std::min<int64_t>(Bt, 16384);  // also bounds the rows a tile may need to redo
+    // whole 64-query groups per tile: phase 2 runs a wave per 64 queries of
+    // a document, so a tile of 64 g + r queries pays a full group for r
+    if (Bt >= 64) Bt = Bt / 64 * 64;
     const int64_t nq = std::min<int64_t>(Bt, Q.B - q0);
     float2* ZW;
     if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * db.v_used * 2 * zw_pairs(KT), ZW))) return rc;
@@ -598,40 +601,22 @@ int docs_as_queries(lcemd_ctx* c, QDev& Q) {
 // row u, which is what that D2Q computes.
 int run_q2d_lc(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
   const int64_t B = Q.B, H = Q.nnz;
-  std::vector<int32_t> col(H);
-  std::vector<float> val(H);
-  HIPCHK(c, hipMemcpyAsync(col.data(), Q.col, sizeof(int32_t) * H, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(val.data(), Q.val, sizeof(float) * H, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  std::vector<int32_t> used(col);
-  std::sort(used.begin(), used.end());
-  used.erase(std::unique(used.begin(), used.end()), used.end());
-  const int64_t nu = (int64_t)used.size();
-  std::vector<int2> cv(H);
-  std::vector<float> xmax(nu, 0.f);
-  for (int64_t i = 0; i < H; ++i) {
-    const int32_t p = (int32_t)(std::lower_bound(used.begin(), used.end(), col[i]) - used.begin());
-    cv[i].x = p;
-    memcpy(&cv[i].y, &val[i], sizeof(float));
-    xmax[p] = std::max(xmax[p], val[i]);
-  }
-  std::vector<int32_t> perm(B);
-  for (int64_t r = 0; r < B; ++r) perm[r] = (int32_t)r;
-  const auto& hp = Q.hptr;
-  for (int64_t w0 = 0; w0 < B; w0 += 128)
-    std::stable_sort(perm.begin() + w0, perm.begin() + std::min<int64_t>(B, w0 + 128),
-                     [&](int32_t x, int32_t y) { return hp[x + 1] - hp[x] < hp[y + 1] - hp[y]; });
+  const int64_t cap = std::min<int64_t>(H, c->v);
   int2* dcv;
   int32_t *dused, *dperm;
   float* dxmax;
+  int *dscr, *dnu;
   int rc;
-  if ((rc = wsget(c, "rev_xcv", (size_t)H, dcv)) || (rc = wsget(c, "rev_used", (size_t)nu, dused)) ||
-      (rc = wsget(c, "rev_xmax", (size_t)nu, dxmax)) || (rc = wsget(c, "rev_perm", (size_t)B, dperm)))
+  if ((rc = wsget(c, "rev_xcv", (size_t)H, dcv)) || (rc = wsget(c, "rev_used", (size_t)cap, dused)) ||
+      (rc = wsget(c, "rev_xmax", (size_t)cap, dxmax)) || (rc = wsget(c, "rev_perm", (size_t)B, dperm)) ||
+      (rc = wsget(c, "rev_scratch", (size_t)reverse_scratch_ints(c->v), dscr)) || (rc = wsget(c, "rev_nu", 1, dnu)))
     return rc;
-  HIPCHK(c, hipMemcpyAsync(dcv, cv.data(), sizeof(int2) * H, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(dused, used.data(), sizeof(int32_t) * nu, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(dxmax, xmax.data(), sizeof(float) * nu, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_reverse_records(Q.ptr, Q.col, Q.val, B, H, c->v, dscr, dcv, dused, dxmax, dperm, dnu, c->stream));
+  // the used word count sizes the tables and phase 1's grid
+  int nu = 0;
+  HIPCHK(c, hipMemcpyAsync(&nu, dnu, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (nu < 1 || nu > cap) return fail(c, LCEMD_E_HIP, "internal: reverse records counted %d used words", nu);
   DbView d;
   d.n = B;
   d.nnz = H;
@@ -647,7 +632,6 @@ int run_q2d_lc(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o, float* out, int
   float* T;
   if ((rc = wsget(c, "rev_out", (size_t)c->n * B, T))) return rc;
   if ((rc = run_d2q(c, d, docs, o, T, B))) return rc;  // T[u * B + b]
-  HIPCHK(c, hipStreamSynchronize(c->stream));           // host vectors above stay alive until here
   HIPCHK(c, launch_transpose(T, c->n, B, out, ld, c->stream));
   return LCEMD_OK;
 }

@@ -182,6 +182,13 @@ hipError_t launch_unpack_topl(const uint64_t* cand, int64_t cand_ld, int64_t row
                               hipStream_t s);
 hipError_t launch_max_inplace(float* a, const float* b, int64_t count, hipStream_t s);
 hipError_t launch_record_weights(const int2* xcv, int64_t nnz, float* val, hipStream_t s);
+// Records of a query batch as the set phase 2 walks (reverse.hip): scratch
+// holds reverse_scratch_ints(v) ints; used / xmax hold up to min(H, v)
+// entries, cv H, perm B; *nu (device) gets the used word count.
+int64_t reverse_scratch_ints(int64_t v);
+hipError_t launch_reverse_records(const int64_t* ptr, const int32_t* col, const float* val, int64_t B, int64_t H,
+                                  int64_t v, int* scratch, int2* cv, int32_t* used, float* xmax, int32_t* perm,
+                                  int* nu, hipStream_t s);
 // in-place n x n: mode 0 transpose, 1 symmetric maximum
 hipError_t launch_square_pair(float* D, int64_t n, int mode, hipStream_t s);
 // out[c * ld_out + r] = in[r * cols + c] for a rows x cols row-major `in`

@@ -48,16 +48,19 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
 // kUnroll at a time with their first table pairs loaded together; further
 // pairs are loaded together for every non-zero that still has mass.
 // Entries past a row's sink are never used: the sink leaves no mass.
-// UNI: every lane of the wave is on this document, so its records and the
+// kUni: every lane of the wave is on this document, so its records and the
 // table row offsets are wave-uniform (scalar loads and arithmetic).
-// Otherwise the QL lanes from `glane` on share the document: its first
+// kGroup: the QL >= 8 lanes from `glane` on share the document: its first
 // lanes load one record each and the group reads them by lane shuffle
-// (every lane of the group runs this with the same e0, e1).
-template <bool UNI>
+// (every lane of the group runs this with the same e0, e1).  kSolo (QL < 8):
+// every lane loads its document's records itself.
+enum { kUni = 0, kGroup = 1, kSolo = 2 };
+template <int RM>
 __device__ __forceinline__ float doc_cost(int64_t e0, int64_t e1, const int2* __restrict__ xcv,
                                           const float4* __restrict__ Zq, int64_t zw_nq, int KP,
                                           int lane, int glane) {
   static_assert(kUnroll == 8, "the group sum below is a tree over 8 terms");
+  constexpr bool UNI = RM == kUni;
   if constexpr (UNI) {
     e0 = uniform64(e0);
     e1 = uniform64(e1);
@@ -75,7 +78,7 @@ __device__ __forceinline__ float doc_cost(int64_t e0, int64_t e1, const int2* __
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) cv[k] = k < cnt ? xcv[e + k] : make_int2(0, 0);
       }
-    } else {
+    } else if constexpr (RM == kGroup) {
       const int j = lane - glane;
       const int2 rec = j < cnt ? xcv[e + j] : make_int2(0, 0);
 #pragma unroll
@@ -83,6 +86,9 @@ __device__ __forceinline__ float doc_cost(int64_t e0, int64_t e1, const int2* __
         cv[k].x = __shfl(rec.x, glane + k);
         cv[k].y = __shfl(rec.y, glane + k);
       }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) cv[k] = k < cnt ? xcv[e + k] : make_int2(0, 0);
     }
     const float4* base[kUnroll];
     float4 f[kUnroll];
@@ -130,7 +136,10 @@ __device__ __forceinline__ float doc_cost(int64_t e0, int64_t e1, const int2* __
 // documents) items from eight work counters, one per XCD, each walking a
 // contiguous eighth of the items, query group major (an XCD keeps one
 // group's slice of the tables hot in its L2).  For fixed-shape batches the
-// live query count is read from device memory.  Every wave exits once its
+// live query count is read from device memory, and the launcher issues one
+// kernel per lane width: the one whose band (QL/2, QL] holds the live count
+// works, the others return at once (so a batch with few live queries does
+// not pay for the lanes of its empty slots).  Every wave exits once its
 // counter passes the end of its range.
 template <int QL>
 __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
@@ -143,6 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
   const int lane = threadIdx.x & 63, qs = lane % QL, ds = lane / QL;
   const int xcd = blockIdx.x & 7;
   const int64_t nq = nq_dev ? (int64_t)*nq_dev : nq_arg;
+  if (nq_dev && (nq > nq_arg || (QL > 1 && 2 * nq <= QL))) return;  // another width's band
   const int64_t nd = (n + kDocs - 1) / kDocs;
   const int64_t total = (nq + QL - 1) / QL * nd;
   const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
@@ -168,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
       for (int j = 0; j < kItemSlots; ++j) {
         const int64_t i = d0 + j;
         if (i >= n) break;
-        sw[j][lane] = doc_cost<true>(xptr[i], xptr[i + 1], xcv, Zq, zw_nq, KP, lane, 0);
+        sw[j][lane] = doc_cost<kUni>(xptr[i], xptr[i + 1], xcv, Zq, zw_nq, KP, lane, 0);
         ++cnt;
       }
       if (qok && cnt > 0) {
@@ -186,7 +196,8 @@ __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
         const int64_t i = d0 + (int64_t)j * S;
         if (i >= n) break;
         const int64_t u = (int64_t)perm[i];
-        const float c = doc_cost<false>(xptr[u], xptr[u + 1], xcv, Zq, zw_nq, KP, lane, ds * QL);
+        const float c = doc_cost<(QL >= kUnroll ? kGroup : kSolo)>(xptr[u], xptr[u + 1], xcv, Zq, zw_nq, KP,
+                                                                   lane, ds * QL);
         if (qok) out[q * ld + u] = c;
       }
     }
@@ -262,11 +273,26 @@ hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_
   if (n <= 0 || nq <= 0) return hipSuccess;
   hipError_t e = launch_zero_ints((int*)counters, 16, s);
   if (e != hipSuccess) return e;
-  if (nq > 32) return launch_p2<64>(xptr, xcv, n, perm, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
-  if (!perm) return hipErrorInvalidValue;
-  if (nq > 16) return launch_p2<32>(xptr, xcv, n, perm, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
-  if (nq > 8) return launch_p2<16>(xptr, xcv, n, perm, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
-  return launch_p2<8>(xptr, xcv, n, perm, ZW, zw_nq, KT, nq, nq_dev, out, ld, counters, s);
+  if (nq <= 32 && !perm) return hipErrorInvalidValue;
+  // lane width: the smallest power of two >= the queries (at most 64); with
+  // a device-side live count, every width up to that one (each works only
+  // for live counts in its band)
+  int top = 1;
+  while (top < 64 && top < nq) top *= 2;
+  for (int ql = top; ql >= (nq_dev ? 1 : top); ql /= 2) {
+    const int64_t qmax = ql == top ? nq : std::min<int64_t>(nq, ql);  // the most queries this width takes
+    switch (ql) {
+      case 64: e = launch_p2<64>(xptr, xcv, n, perm, ZW, zw_nq, KT, qmax, nq_dev, out, ld, counters, s); break;
+      case 32: e = launch_p2<32>(xptr, xcv, n, perm, ZW, zw_nq, KT, qmax, nq_dev, out, ld, counters, s); break;
+      case 16: e = launch_p2<16>(xptr, xcv, n, perm, ZW, zw_nq, KT, qmax, nq_dev, out, ld, counters, s); break;
+      case 8: e = launch_p2<8>(xptr, xcv, n, perm, ZW, zw_nq, KT, qmax, nq_dev, out, ld, counters, s); break;
+      case 4: e = launch_p2<4>(xptr, xcv, n, perm, ZW, zw_nq, KT, qmax, nq_dev, out, ld, counters, s); break;
+      case 2: e = launch_p2<2>(xptr, xcv, n, perm, ZW, zw_nq, KT, qmax, nq_dev, out, ld, counters, s); break;
+      default: e = launch_p2<1>(xptr, xcv, n, perm, ZW, zw_nq, KT, qmax, nq_dev, out, ld, counters, s); break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 __global__ __launch_bounds__(kThreads) void k_max_inplace(float* a, const float* b, int64_t count) {

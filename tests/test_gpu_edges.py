@@ -199,7 +199,8 @@ def test_batch_lanes_with_unaligned_rows_and_short_tail(L):
     a time) against 150 documents: output rows of odd queries start off a
     16-byte boundary and the last item of each row holds 6 documents.  The
     distances equal the oracle's, and bit for bit those of 5-query batches
-    (8 query lanes, stored one by one)."""
+    (8 query lanes, stored one by one) and of 1-4-query batches (1, 2 or 4
+    query lanes, records loaded per lane)."""
     from synth import make_workload
 
     w = make_workload("tiny", n=150, B=40)
@@ -214,3 +215,11 @@ def test_batch_lanes_with_unaligned_rows_and_short_tail(L):
             s = q.take(list(range(b0, b0 + 5)))
             part = ctx.distances(s.rowptr, s.col, s.val, method=method, k=k, direction="d2q")
             assert np.array_equal(part, g[b0:b0 + 5]), (method, b0)
+        # batches of 1-4 queries: one, two or four query lanes per document
+        # (each lane loads its document's records itself)
+        b0 = 0
+        for size in (1, 2, 3, 4, 1, 4):
+            s = q.take(list(range(b0, b0 + size)))
+            part = ctx.distances(s.rowptr, s.col, s.val, method=method, k=k, direction="d2q")
+            assert np.array_equal(part, g[b0:b0 + size]), (method, b0, size)
+            b0 += size
