@@ -419,11 +419,11 @@ def serve_sweep(a, lcemd, ctx, v, n):
     10-500-word queries (ACT k=8, symmetric top-16), each offered rate for
     about --serve-seconds, rising until the path saturates (achieved rate
     below 90 % of the offered one), plus a saturation burst.  Three paths:
-    bf16 keys on four launch lanes (continuous batching: a free lane takes
-    the waiting queries at once, so up to four batches run side by side),
-    bf16 keys on one lane, and float32 keys on one lane -- precision and
-    lane policy each change alone between two of them.  Latency =
-    completion - scheduled arrival."""
+    bf16 keys on one launch lane (the default: the next batch starts the
+    moment the previous one ends, with every query that arrived meanwhile),
+    bf16 keys on four lanes (up to four batches side by side), and float32
+    keys on one lane -- precision and lane count each change alone between
+    two of them.  Latency = completion - scheduled arrival."""
     import threading
 
     import numpy as np
@@ -437,7 +437,7 @@ def serve_sweep(a, lcemd, ctx, v, n):
     out = {"setup": (f"Poisson arrivals, 10-500 words per query, up to {a.serve_slots} queries per batch; each "
                      f"rate offered for ~{a.serve_seconds:g} s (200-3,000 queries) until saturation; saturation = "
                      f"{a.serve_sat} queries submitted at once")}
-    for name, prec, graph, lanes in (("bf16", "bf16", True, 4), ("bf16_1lane", "bf16", True, 1),
+    for name, prec, graph, lanes in (("bf16", "bf16", True, 1), ("bf16_4lanes", "bf16", True, 4),
                                      ("fp32", "fp32", False, 1)):
         srv = lcemd.Server(ctx, method="act", k=8, precision=prec, l=16, max_slots=a.serve_slots,
                            memory_budget=a.serve_budget << 30, use_graph=graph, lanes=lanes)

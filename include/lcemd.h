@@ -271,7 +271,11 @@ int lcemd_profile_get(lcemd_ctx* ctx, lcemd_phase_time* out, int cap);
  * queries wait, the lane takes the FIFO head's queries (as many as fit its
  * B slots and W words) and launches at once -- no batch waits to fill, and
  * queries that arrive while other batches run join the next free lane, so
- * up to `lanes` batches overlap on the device.  A batch runs phase 1
+ * up to `lanes` batches overlap on the device.  One lane is the default: a
+ * batch's phase-1 and phase-2 kernels each fill every CU, so overlapping
+ * batches add no throughput and lengthen each other; with one lane the
+ * next batch starts the moment the previous one ends, with every query
+ * that arrived meanwhile.  A batch runs phase 1
  * tables, the exact redo of uncertified rows, phase 2 on a persistent
  * kernel fed by per-XCD work counters, D2Q candidate selection, Q2D of the
  * candidates and the symmetric top-l, and completes each query
@@ -300,7 +304,7 @@ typedef struct {
   int64_t memory_budget;   /* device bytes for all lanes' buffers; 0 = 4 GiB */
   int32_t use_graph;       /* nonzero: each lane's batch replayed as a captured hipGraph;
                               zero: kernels launched per batch */
-  int32_t lanes;           /* batches in flight, 0..16; 0 = 4 with use_graph, 1 without */
+  int32_t lanes;           /* batches in flight, 0..16; 0 = 1 (see above) */
   int32_t reserved[4];     /* must be 0 */
 } lcemd_server_cfg;
 

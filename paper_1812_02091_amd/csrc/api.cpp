@@ -59,6 +59,9 @@ void free_db(lcemd_ctx* c) {
   dfree((void*&)c->xcol);
   dfree((void*&)c->used);
   dfree((void*&)c->xmax);
+  dfree((void*&)c->wptr);
+  dfree((void*&)c->wwt);
+  dfree((void*&)c->winv);
   c->n = c->nnz = c->v_used = 0;
   c->db_hmax = 0;
   c->used_host.clear();
@@ -398,6 +401,9 @@ struct DbView {
   const int32_t* used = nullptr; // compact id -> word id
   const float* xmax = nullptr;   // largest weight of each used word
   const int32_t* perm = nullptr; // rows by length within windows of 128
+  const int64_t* wptr = nullptr; // weights by word (the loaded database only)
+  const float* wwt = nullptr;
+  const uint32_t* winv = nullptr;
 };
 
 DbView db_view(lcemd_ctx* c) {
@@ -411,7 +417,29 @@ DbView db_view(lcemd_ctx* c) {
   d.used = c->used;
   d.xmax = c->xmax;
   d.perm = c->xperm;
+  d.wptr = c->wptr;
+  d.wwt = c->wwt;
+  d.winv = c->winv;
   return d;
+}
+
+// Word-major phase 2 for a tile: when the database has its by-word records,
+// the lists fit (KT <= 16), and one 64-query group's tables (v_used x KP x
+// 1 KiB) are far beyond the caches -- there the per-document walk re-reads
+// a word's run from HBM for every document holding it -- and the cost
+// scratch (nnz x 256 bytes) fits in free device memory.
+bool use_word_major(lcemd_ctx* c, const DbView& db, int KT) {
+  if (!db.wwt || c->p2_mode == 2 || KT > 16 || db.nnz > 0xffffffffLL) return false;
+  if (c->p2_mode != 1 && (double)db.v_used * (double)zw_pairs(KT) * 1024.0 < 1e9) return false;
+  const auto it = c->ws.find("p2_cost");
+  const size_t need = (size_t)db.nnz * 64 * sizeof(float);
+  if (it != c->ws.end() && it->second.bytes >= need) return true;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return fr > need + (size_t(2) << 30);
 }
 
 P1Args base_args(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o) {
@@ -518,9 +546,21 @@ int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, 
     const double a2 = (double)nq * (8.0 * db.nnz + 8.0 * (db.n + 1) + 8.0 * (double)db.v_used * KT + 4.0 * db.n);
     if ((rc = prof_begin(c, "phase2", a2))) return rc;
     unsigned long long* p2c;
-    if ((rc = wsget(c, "p2_counters", 8, p2c))) return rc;
-    HIPCHK(c, launch_phase2_persistent(db.xptr, db.xcv, db.n, db.perm, ZW, a.zw_nq, KT, nq, nullptr,
-                                       out + q0 * ld, ld, p2c, c->stream));
+    if ((rc = wsget(c, "p2_counters", 16, p2c))) return rc;
+    // whole 64-query groups word-major where that pays, the rest (and every
+    // group otherwise) per document; both give the same bits
+    const int64_t ng = !c->arena.base && use_word_major(c, db, KT) ? nq / 64 : 0;
+    if (ng > 0) {
+      float* cost;
+      if ((rc = wsget(c, "p2_cost", (size_t)db.nnz * 64, cost))) return rc;
+      for (int64_t g = 0; g < ng; ++g)
+        HIPCHK(c, launch_phase2_wordmajor(db.xptr, db.n, db.wptr, db.wwt, db.winv, db.nnz, db.v_used,
+                                          ZW + 2 * 64 * g, a.zw_nq, KT, cost, out + (q0 + 64 * g) * ld, ld, p2c,
+                                          c->stream));
+    }
+    if (nq > 64 * ng)
+      HIPCHK(c, launch_phase2_persistent(db.xptr, db.xcv, db.n, db.perm, ZW + 2 * 64 * ng, a.zw_nq, KT, nq - 64 * ng,
+                                         nullptr, out + (q0 + 64 * ng) * ld, ld, p2c, c->stream));
     if ((rc = prof_end(c))) return rc;
     q0 += nq;
     prec = o->precision;
@@ -691,6 +731,7 @@ int lcemd_create(lcemd_ctx** out, int device) {
   c->scratch_rc = noalloc_setup(device, &c->scratch);
   if (const char* fk = getenv("LCEMD_FORCE_KERNEL")) c->force_kernel = atoi(fk);
   if (const char* sc = getenv("LCEMD_SYM_CANDIDATES")) c->sym_candidates = atoi(sc);
+  if (const char* p2 = getenv("LCEMD_PHASE2")) c->p2_mode = atoi(p2);
   *out = c;
   return LCEMD_OK;
 }
@@ -860,6 +901,30 @@ int lcemd_load_database(lcemd_ctx* c, const int64_t* rowptr, const int32_t* col,
   }
   HIPCHK(c, hipMemcpy(c->used, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->xmax, xmax.data(), sizeof(float) * used.size(), hipMemcpyHostToDevice));
+  if (nnz <= 0xffffffffLL) {
+    // the records grouped by word (CSR order within a word) for the
+    // word-major phase 2
+    const int64_t nu = (int64_t)used.size();
+    std::vector<int64_t> wp(nu + 1, 0);
+    for (int64_t i = 0; i < nnz; ++i) ++wp[cv[i].x + 1];
+    for (int64_t p = 0; p < nu; ++p) wp[p + 1] += wp[p];
+    std::vector<int64_t> fill(wp.begin(), wp.end() - 1);
+    std::vector<float> ww(nnz);
+    std::vector<uint32_t> inv(nnz);
+    for (int64_t i = 0; i < nnz; ++i) {
+      const int64_t e = fill[cv[i].x]++;
+      memcpy(&ww[e], &cv[i].y, sizeof(float));
+      inv[i] = (uint32_t)e;
+    }
+    if ((rc = dalloc(c, c->wptr, nu + 1, "word offsets")) || (rc = dalloc(c, c->wwt, nnz, "weights by word")) ||
+        (rc = dalloc(c, c->winv, nnz, "by-word index"))) {
+      free_db(c);
+      return rc;
+    }
+    HIPCHK(c, hipMemcpy(c->wptr, wp.data(), sizeof(int64_t) * (nu + 1), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->wwt, ww.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->winv, inv.data(), sizeof(uint32_t) * nnz, hipMemcpyHostToDevice));
+  }
   c->n = n;
   c->nnz = nnz;
   c->v_used = (int64_t)used.size();

@@ -58,6 +58,12 @@ struct lcemd_ctx {
   int2* xcv = nullptr;
   int32_t* xcol = nullptr;
   int32_t* xperm = nullptr;  // database rows by length within windows of 128
+  // the weights grouped by compact word id (word-major phase 2): wptr[v_used
+  // + 1] offsets into wwt (CSR order within a word); winv[i] = the by-word
+  // index of CSR non-zero i
+  int64_t* wptr = nullptr;
+  float* wwt = nullptr;
+  uint32_t* winv = nullptr;
   int32_t* used = nullptr;
   float* xmax = nullptr;
   std::vector<int32_t> used_host;
@@ -67,6 +73,7 @@ struct lcemd_ctx {
   size_t table_budget = size_t(12) << 30;
   int force_kernel = 0;   // test hook (LCEMD_FORCE_KERNEL): 1 = skip the 128-row kernel, 2 = deep kernel
   int sym_candidates = 0; // test hook (LCEMD_SYM_CANDIDATES): first candidate count of the SYM top-l
+  int p2_mode = 0;        // test hook (LCEMD_PHASE2): 0 = by table size, 1 = word-major when possible, 2 = per document
   int64_t fallbacks = 0;  // tiles redone with float32 keys / deeper lists
   int64_t fixed_rows = 0; // bf16 table rows redone exactly one by one
   // allocation-free calls: this device's scratch region and the arena over it

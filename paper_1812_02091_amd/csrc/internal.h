@@ -201,6 +201,15 @@ int persistent_grid(const void* kernel, int threads, size_t shmem, int64_t items
 // not null (fixed-shape batches; nq is then its largest value), else nq.
 // perm: the documents in order of length (used for batches of up to 32
 // queries).  counters: 8 u64, zeroed here.
+// Word-major phase 2 (phase2.hip) for one group of 64 queries: wptr[v_used
+// + 1] / wwt = the database's weights grouped by compact word id (CSR
+// order within a word, every word with at least one), winv[i] = the
+// by-word index of CSR non-zero i; cost: nnz x 64 floats of scratch; ZW
+// and out start at the group's first query; KT <= 16; counters: 16 u64.
+hipError_t launch_phase2_wordmajor(const int64_t* xptr, int64_t n, const int64_t* wptr, const float* wwt,
+                                   const uint32_t* winv, int64_t nnz, int64_t v_used, const float2* ZW,
+                                   int64_t zw_nq, int KT, float* cost, float* out, int64_t ld,
+                                   unsigned long long* counters, hipStream_t s);
 hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_t n, const int32_t* perm,
                                     const float2* ZW, int64_t zw_nq, int KT, int64_t nq,
                                     const int* nq_dev, float* out, int64_t ld,

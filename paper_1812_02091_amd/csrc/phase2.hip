@@ -31,9 +31,12 @@ constexpr int kUnroll = 8;       // non-zeros whose table loads are in flight to
 constexpr int kItemSlots = 16;   // document slots per lane and work item
 static_assert(kItemSlots % 4 == 0, "results are stored four at a time");
 
-// One transfer step of Eq. (6)-(8) against table entry (z, w).
+// One transfer step of Eq. (6)-(8) against table entry (z, w).  rem >= +0
+// (never -0: rem - rem is +0) and w > 0 (or +inf), so the smaller float is
+// the smaller bit pattern: one integer minimum (fminf would first
+// canonicalise both operands).
 __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
-  const float r = fminf(rem, w);
+  const float r = __uint_as_float(min(__float_as_uint(rem), __float_as_uint(w)));
   rem -= r;
   acc = fmaf(r, z, acc);
 }
@@ -293,6 +296,231 @@ hipError_t launch_phase2_persistent(const int64_t* xptr, const int2* xcv, int64_
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Word-major phase 2 for large vocabularies.  When a query group's tables
+// are far larger than the caches, the per-document walk above re-reads a
+// word's table run from HBM for every document that holds the word.  Here
+// the same transfers run in two passes over one group of 64 queries:
+//  A. the database's non-zeros word by word (their weights grouped by word,
+//     made at load): a wave keeps the 64 queries' table run of the current
+//     word in registers (pairs loaded as some lane's walk first needs them)
+//     and writes each non-zero's 64 costs as one 256-byte row, in the same
+//     by-word order (a sequential stream);
+//  B. the documents in order: every (query, document) sum takes the costs
+//     of its non-zeros in CSR order (each non-zero's by-word index from a
+//     map made at load) with the grouping and compensation of doc_cost
+//     (eight-term trees, Kahan across groups).
+// The walk in A is the same sequence of step() calls as in doc_cost, so
+// the results are the same bits whichever phase 2 ran.
+constexpr int kWmSpan = 2048;  // non-zeros per pass-A wave (a fixed range: no work counter)
+
+// Pass A.  Wave w takes the by-word records [w kWmSpan, (w + 1) kWmSpan),
+// which may span many words; a lane per query.  The next two words' first
+// table pairs and end offsets are in flight while the current word runs,
+// and the next 64 weights while the current 64 are walked.
+template <int KPM>
+__global__ __launch_bounds__(kThreads) void k_p2_word_costs(
+    const int64_t* __restrict__ wptr, const float* __restrict__ wwt, int64_t nnz, int64_t v_used,
+    const float4* __restrict__ ZP, int64_t zw_nq, int KP, float* __restrict__ cost) {
+  const int lane = threadIdx.x & 63;
+  const int64_t gw = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int64_t e0 = gw * kWmSpan, e1 = min(nnz, e0 + kWmSpan);
+  if (e0 >= e1) return;
+  // the word of e0: the last p with wptr[p] <= e0 (wave-uniform search)
+  int64_t lo = 0, hi = v_used;  // wptr[lo] <= e0 < wptr[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (uniform64(wptr[mid]) <= e0) lo = mid;
+    else hi = mid;
+  }
+  int64_t word = lo;
+  int64_t wend = uniform64(wptr[word + 1]);
+  // indices past the last word are clamped to it: those loads are never used
+  // (no record lies past the last word), and plain loads of valid rows keep
+  // the compiler from selecting between pointers
+  const int64_t lastw = v_used - 1;
+  int64_t nend = uniform64(wptr[min(word + 2, v_used)]);
+  int64_t nend2 = uniform64(wptr[min(word + 3, v_used)]);
+  const int64_t rs = (int64_t)KP * zw_nq;  // float4s from one word's run to the next
+  const float4* run = ZP + word * rs + lane;
+  float4 f[KPM];
+  f[0] = run[0];
+  float4 fn = ZP[min(word + 1, lastw) * rs + lane];
+  float4 fn2 = ZP[min(word + 2, lastw) * rs + lane];
+  int loaded = 1;
+  // weights come 64 at a time, one per lane (the next 64 in flight while
+  // these are walked), and are read out to every lane by readlane
+  float wcur = e0 + lane < e1 ? wwt[e0 + lane] : 0.f, wnext = 0.f;
+  for (int64_t e = e0; e < e1; e += kUnroll) {
+    const int cnt = (int)min((int64_t)kUnroll, e1 - e);
+    const int off = (int)((e - e0) & 63);
+    if (off == 0 && e + 64 < e1) wnext = e + 64 + lane < e1 ? wwt[e + 64 + lane] : 0.f;
+    const float wcur0 = wcur;  // this batch's block of weights
+    float rec[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k)
+      rec[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wcur), off + k));
+    if (off + kUnroll == 64) wcur = wnext;
+    float* cb = cost + e * 64 + lane;  // this batch's cost rows (offsets k * 256 bytes)
+    if (e + cnt <= wend) {
+      // the whole batch on the current word: the eight walks side by side,
+      // pair by pair (the same steps per walk as one at a time)
+      float rem[kUnroll], acc[kUnroll];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        rem[k] = k < cnt ? rec[k] : 0.f;
+        acc[k] = 0.f;
+        step(rem[k], acc[k], f[0].x, f[0].y);
+        if (rem[k] > 0.f) step(rem[k], acc[k], f[0].z, f[0].w);
+        any = any || rem[k] > 0.f;
+      }
+#pragma unroll
+      for (int p = 1; p < KPM; ++p) {
+        if (p >= KP || !__any(any)) break;
+        if (p >= loaded) {
+          f[p] = run[p * zw_nq];
+          loaded = p + 1;
+        }
+        any = false;
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+          if (rem[k] > 0.f) {
+            step(rem[k], acc[k], f[p].x, f[p].y);
+            if (rem[k] > 0.f) step(rem[k], acc[k], f[p].z, f[p].w);
+            any = any || rem[k] > 0.f;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k)
+        if (k < cnt) cb[k * 64] = acc[k];
+      continue;
+    }
+    // the batch crosses into later words: one walk at a time
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      if (k >= cnt) break;
+      const int64_t ee = e + k;
+      if (ee >= wend) {  // the next word (wave-uniform)
+        ++word;
+        if (ee < nend) {
+          f[0] = fn;
+          fn = fn2;
+          wend = nend;
+          nend = nend2;
+        } else {  // words without records (none in a loaded database): search on
+          while (uniform64(wptr[word + 1]) <= ee) ++word;
+          wend = uniform64(wptr[word + 1]);
+          f[0] = ZP[word * rs + lane];
+          fn = ZP[min(word + 1, lastw) * rs + lane];
+          nend = uniform64(wptr[min(word + 2, v_used)]);
+        }
+        run = ZP + word * rs + lane;
+        loaded = 1;
+        nend2 = uniform64(wptr[min(word + 3, v_used)]);
+        fn2 = ZP[min(word + 2, lastw) * rs + lane];
+      }
+      float rem = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wcur0), off + k)), acc = 0.f;
+      step(rem, acc, f[0].x, f[0].y);
+      if (rem > 0.f) step(rem, acc, f[0].z, f[0].w);
+#pragma unroll
+      for (int p = 1; p < KPM; ++p) {
+        if (p >= KP || !__any(rem > 0.f)) break;
+        if (p >= loaded) {  // the first walk to reach this pair loads it for the wave
+          f[p] = run[p * zw_nq];
+          loaded = p + 1;
+        }
+        if (rem > 0.f) {
+          step(rem, acc, f[p].x, f[p].y);
+          if (rem > 0.f) step(rem, acc, f[p].z, f[p].w);
+        }
+      }
+      cb[k * 64] = acc;
+    }
+  }
+}
+
+// Pass B: one wave per kItemSlots consecutive documents, a lane per query.
+__global__ __launch_bounds__(kThreads) void k_p2_doc_sums(const int64_t* __restrict__ xptr, int64_t n,
+                                                          const uint32_t* __restrict__ winv,
+                                                          const float* __restrict__ cost, float* __restrict__ out,
+                                                          int64_t ld, unsigned long long* __restrict__ counters) {
+  __shared__ float st[kThreads / 64][kItemSlots][64];
+  float(*sw)[64] = st[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
+  const int xcd = blockIdx.x & 7;
+  const int64_t total = (n + kItemSlots - 1) / kItemSlots;
+  const int64_t lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
+  while (true) {
+    unsigned long long it = 0;
+    if (lane == 0) it = atomicAdd(&counters[8 + xcd], 1ull);
+    const int64_t item = lo + (int64_t)__shfl((long long)it, 0);
+    if (item >= hi) break;
+    const int64_t d0 = item * kItemSlots;
+    int cnt = 0;
+    for (int j = 0; j < kItemSlots; ++j) {
+      const int64_t u = d0 + j;
+      if (u >= n) break;
+      const int64_t e0 = uniform64(xptr[u]), e1 = uniform64(xptr[u + 1]);
+      float t = 0.f, comp = 0.f;
+      int wv = 0;  // 64 by-word indices at a time, one per lane
+      for (int64_t e = e0; e < e1; e += kUnroll) {
+        const int c8 = (int)min((int64_t)kUnroll, e1 - e);
+        const int off = (int)((e - e0) & 63);
+        if (off == 0) wv = e + lane < e1 ? (int)winv[e + lane] : 0;
+        float x[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+          const uint32_t wi = (uint32_t)__builtin_amdgcn_readlane(wv, off + k);
+          x[k] = k < c8 ? cost[(int64_t)wi * 64 + lane] : 0.f;
+        }
+        const float g = ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
+        const float y = g - comp;
+        const float tt = t + y;
+        comp = (tt - t) - y;
+        t = tt;
+      }
+      sw[j][lane] = t;
+      ++cnt;
+    }
+    float* o = out + (int64_t)lane * ld + d0;
+    if (cnt == kItemSlots && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+#pragma unroll
+      for (int t = 0; t < kItemSlots; t += 4)
+        *reinterpret_cast<float4*>(o + t) = make_float4(sw[t][lane], sw[t + 1][lane], sw[t + 2][lane], sw[t + 3][lane]);
+    } else {
+      for (int t = 0; t < cnt; ++t) o[t] = sw[t][lane];
+    }
+  }
+}
+
+hipError_t launch_phase2_wordmajor(const int64_t* xptr, int64_t n, const int64_t* wptr, const float* wwt,
+                                   const uint32_t* winv, int64_t nnz, int64_t v_used, const float2* ZW,
+                                   int64_t zw_nq, int KT, float* cost, float* out, int64_t ld,
+                                   unsigned long long* counters, hipStream_t s) {
+  // one group of 64 queries: ZW and out start at the group's first query
+  const int KP = (int)zw_pairs(KT);
+  if (n <= 0 || nnz <= 0 || v_used <= 0) return hipSuccess;
+  if (KP > 8 || nnz > 0xffffffffLL) return hipErrorInvalidValue;
+  hipError_t e = launch_zero_ints((int*)counters, 32, s);
+  if (e != hipSuccess) return e;
+  const int64_t waves = (nnz + kWmSpan - 1) / kWmSpan;
+  const dim3 ga((unsigned)((waves + kThreads / 64 - 1) / (kThreads / 64)));
+  if (KP <= 4)
+    hipLaunchKernelGGL(k_p2_word_costs<4>, ga, dim3(kThreads), 0, s, wptr, wwt, nnz, v_used, (const float4*)ZW,
+                       zw_nq, KP, cost);
+  else
+    hipLaunchKernelGGL(k_p2_word_costs<8>, ga, dim3(kThreads), 0, s, wptr, wwt, nnz, v_used, (const float4*)ZW,
+                       zw_nq, KP, cost);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t itemsB = (n + kItemSlots - 1) / kItemSlots;
+  const int gb = persistent_grid((const void*)k_p2_doc_sums, kThreads, 0, (itemsB + 3) / 4);
+  if (gb <= 0) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_p2_doc_sums, dim3(gb), dim3(kThreads), 0, s, xptr, n, winv, cost, out, ld, counters);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kThreads) void k_max_inplace(float* a, const float* b, int64_t count) {

@@ -444,7 +444,7 @@ int lcemd_server_start(lcemd_ctx* c, const lcemd_server_cfg* cfg, lcemd_server**
   s->cld = s->use < c->n ? s->use + 1 : s->use;
   if (s->cld > kSelectBuf / 2) s->use = kSelectBuf / 2 - 1, s->cld = s->use + 1;
   // admission by device memory: lanes x slots x per-query state <= budget
-  const int nlanes = cfg->lanes > 0 ? cfg->lanes : (cfg->use_graph ? 4 : 1);
+  const int nlanes = cfg->lanes > 0 ? cfg->lanes : 1;
   const double per_q = (double)c->v_used * zw_pairs(s->KT) * 16 + (double)c->n * 4 + (double)s->cld * 8 +
                        (double)s->use * 4 * (1 + (LCEMD_SERVE_MAX_HIST + kRows - 1) / kRows) + 64.0 * s->l +
                        (double)LCEMD_SERVE_MAX_HIST * 32;

@@ -134,6 +134,43 @@ def test_text_1m_vocabulary(L):
     say("[gpu] 1M-word workload done")
 
 
+def test_text_1m_word_major_phase2(L, monkeypatch):
+    """At the 1M-word size one 64-query group's tables (4 GB at k = 8) are
+    far beyond the caches and phase 2 runs word-major (costs per non-zero,
+    then per-document sums); 130 queries (two whole groups and a 2-query
+    tail on the per-document kernel): the D2Q distances equal the
+    per-document kernel's bit for bit, for ACT k=8 and RWMD."""
+    import torch
+
+    w = make_workload("text-1M", B=130)
+    dev = torch.device("cuda:0")
+    q = [torch.from_numpy(x).to(dev) for x in (w.queries.rowptr, w.queries.col, w.queries.val)]
+    out = {}
+    for mode in ("0", "2"):
+        monkeypatch.setenv("LCEMD_PHASE2", mode)
+        ctx = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val)
+        for method, k in (("act", 8), ("rwmd", 1)):
+            say(f"[gpu] 1M-word D2Q, 130 queries, {method} k={k}, phase-2 mode {mode}")
+            out[mode, method] = ctx.distances(*q, method=method, k=k, direction="d2q")
+        ctx.close()
+    for method in ("act", "rwmd"):
+        a, b = out["0", method], out["2", method]
+        assert torch.equal(a, b), (method, int((a != b).sum()))
+    # and against the float64 oracle on sampled pairs of both groups and the tail
+    bs, us = sample_pairs(6, 130, w.db.n, 12)
+    bs = np.concatenate([bs, [0, 63, 64, 127, 128, 129]])
+    us = np.concatenate([us, [5, 77, 123456, 999999, 314159, 42]])
+    docs = sorted(set(int(u) for u in us))
+    sub = w.db.take(docs)
+    pos = {u: i for i, u in enumerate(docs)}
+    orc = O.Oracle(w.V, sub.rowptr, sub.col, sub.val)
+    d = out["0", "act"]
+    for b, u in zip(bs, us):
+        qc, qw = w.queries.row(int(b))
+        o = orc.pair(qc, qw, pos[int(u)], "act", 8, "d2q")
+        P.assert_distances(np.array([float(d[int(b), int(u)])]), np.array([o]), f"query {b} doc {u}")
+
+
 def certified_row(orc, qc, qw, method, k, tau, tol_frac=1e-5):
     """The oracle's symmetric distances of one query against the whole
     database wherever they can reach the top-l: every document whose

@@ -58,16 +58,16 @@ def _reference(ctx, qs, method, k, prec, ell):
     return ref
 
 
-@pytest.mark.parametrize("prec,graph,method,k", [("fp32", True, "act", 8), ("fp32", False, "act", 8),
-                                                 ("bf16", True, "act", 8), ("fp8", True, "act", 8),
-                                                 ("fp32", True, "ict", 1),
-                                                 ("fp32", True, "omr", 1)])
-def test_server_matches_topl_alone_and_mixed(setup, prec, graph, method, k):
+@pytest.mark.parametrize("prec,graph,method,k,lanes", [("fp32", True, "act", 8, 1), ("fp32", True, "act", 8, 3),
+                                                       ("fp32", False, "act", 8, 1), ("bf16", True, "act", 8, 1),
+                                                       ("bf16", True, "act", 8, 4), ("fp8", True, "act", 8, 1),
+                                                       ("fp32", True, "ict", 1, 2), ("fp32", True, "omr", 1, 1)])
+def test_server_matches_topl_alone_and_mixed(setup, prec, graph, method, k, lanes):
     L, w, qs, ctx = setup
     ell = 16
-    say(f"[gpu] server {prec} graph={graph} {method} k={k}")
+    say(f"[gpu] server {prec} graph={graph} {method} k={k} lanes={lanes}")
     ref = _reference(ctx, qs, method, k, prec, ell)
-    srv = L.Server(ctx, method=method, k=k, precision=prec, l=ell, max_slots=16, use_graph=graph)
+    srv = L.Server(ctx, method=method, k=k, precision=prec, l=ell, max_slots=16, use_graph=graph, lanes=lanes)
     try:
         # each query alone
         alone = {}
@@ -125,8 +125,8 @@ def test_server_memory_budget_too_small(setup):
     assert e.value.code == L.E_CAPACITY
 
 
-@pytest.mark.parametrize("prec,graph", [("bf16", True), ("fp32", False)])
-def test_server_matches_oracle(setup, prec, graph):
+@pytest.mark.parametrize("prec,graph,lanes", [("bf16", True, 1), ("bf16", True, 4), ("fp32", False, 1)])
+def test_server_matches_oracle(setup, prec, graph, lanes):
     """Serving results against whole float64 oracle rows (Sec. 5 top-l,
     ACT k=8 symmetric, m = 300): ten queries of the arrival trace, the
     longest ones (300-500 words) among them, submitted together so that
@@ -135,9 +135,9 @@ def test_server_matches_oracle(setup, prec, graph):
     lens = np.diff(qs.rowptr)
     picks = sorted(set(np.argsort(lens)[-5:].tolist()) | {0, 1, 2, 3, 4})
     assert lens[picks].max() >= 300
-    say(f"[gpu] server vs oracle {prec} graph={graph}: queries of {sorted(lens[picks].tolist())} words")
+    say(f"[gpu] server vs oracle {prec} graph={graph} lanes={lanes}: queries of {sorted(lens[picks].tolist())} words")
     orc = O.Oracle(w.V, w.db.rowptr, w.db.col, w.db.val)
-    srv = L.Server(ctx, method="act", k=8, precision=prec, l=16, max_slots=8, use_graph=graph)
+    srv = L.Server(ctx, method="act", k=8, precision=prec, l=16, max_slots=8, use_graph=graph, lanes=lanes)
     try:
         tickets = [srv.submit(*qs.row(b)) for b in picks]
         got = [srv.wait(t) for t in tickets]
