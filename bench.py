@@ -70,7 +70,7 @@ def phase1_kernel(method, k, precision, m):
     kl = 2
     while kl < depth + margin:
         kl *= 2
-    prec = 0 if margin == 0 else 1
+    prec = 0 if margin == 0 else {"bf16": 1, "fp8": 2}[precision]
     if prec == 0 and (m + 3) // 4 <= 7 and depth <= 64 and method != "ict":  # float32, at most 28 dims: 64-row kernel
         return f"k_phase1_fast<0, {kl}, 0>"
     if depth + margin <= 32:
@@ -78,13 +78,15 @@ def phase1_kernel(method, k, precision, m):
     return "k_phase1_fast<0, 64, 0>" if depth <= 64 else "k_phase1_f32"
 
 
-KERNEL_SOURCES = {"k_phase1_bf16": "phase1_bf16.hip", "k_phase2_persistent": "phase2.hip"}
+KERNEL_SOURCES = {"k_phase1_bf16": "phase1_bf16.hip", "k_phase2_persistent": "phase2.hip",
+                  "k_p2_word_costs": "phase2.hip", "k_p2_doc_sums": "phase2.hip"}
 
 
-def measured_traffic(kernel, a, precision):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    record of this workload (profiles/traffic.json), if it was taken on the
-    current kernel source (its sha256 is recorded with it); otherwise None."""
+def traffic_record(kernel, a, precision):
+    """The committed rocprofv3 --pmc record of `kernel` on this workload
+    (profiles/traffic.json: HBM bytes per launch, launches per step), if it
+    was taken on the current kernel source (its sha256 is recorded with it);
+    otherwise None."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -98,7 +100,34 @@ def measured_traffic(kernel, a, precision):
     e = rec.get(key)
     if not e or e.get("source_sha256") != digest:
         return None
-    return e["bytes_per_launch"]
+    return e
+
+
+def measured_traffic(kernel, a, precision):
+    e = traffic_record(kernel, a, precision)
+    return None if e is None else e["bytes_per_launch"]
+
+
+def phase2_roofline(phases, steps, a, precision):
+    """Phase 2 against HBM: the counted bytes of its kernels per step (the
+    word-major pair on the 1M-word workload, from profiles/traffic.json) over
+    its HIP-event time; beside it the A2 figure (a full pass over the
+    database charged to every query, which the kernels share across 64
+    queries: not a fraction of anything)."""
+    p2 = phases.get("phase2")
+    if not p2 or p2["ms"] <= 0:
+        return None
+    ms = p2["ms"] / steps
+    recs = [traffic_record(k, a, precision) for k in ("k_p2_word_costs", "k_p2_doc_sums")]
+    out = {"bound": "hbm", "ms_per_step": ms, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+           "a2_algorithmic_GBps": p2["work"] / (p2["ms"] * 1e-3) / 1e9}
+    if all(recs):
+        byt = sum(r["bytes_per_launch"] * r["launches_per_step"] for r in recs)
+        out.update({"kernels": "k_p2_word_costs + k_p2_doc_sums", "counted_bytes_per_step": byt,
+                    "achieved": byt / (ms * 1e-3) / 1e9, "frac": byt / (ms * 1e-3) / HBM_PEAK})
+    else:
+        out.update({"achieved": None, "frac": None, "counted_bytes_per_step": None})
+    return out
 
 
 def copy_calibration():
@@ -675,6 +704,7 @@ def main():
                    "global_batch": B, "database": n, "k": a.k, "ell": a.ell,
                    "method": a.method, "direction": a.direction, "parallelism": "single GPU"},
         "roofline": roofline,
+        "phase2_roofline": phase2_roofline(phases, a.steps, a, a.precision),
         "cpu_baseline": cpu,
         "phases": precisions[a.precision]["phases"],
         "precisions": precisions,
