@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "context.h"
+#include "validate.h"
 
 using namespace lcemd;
 
@@ -134,50 +135,19 @@ int prof_collect(lcemd_ctx* c) {
 }
 
 // ------------------------------- validation -------------------------------
-// Host-side check of a CSR histogram batch; returns LCEMD_OK or
-// LCEMD_E_BAD_CSR with a message.  hmax receives the longest row.
+// Host-side check of a CSR histogram batch (validate.h); returns LCEMD_OK
+// or the error with its message.  hmax receives the longest row.
 int check_csr_host(lcemd_ctx* c, const char* what, const int64_t* ptr, const int32_t* col,
                    const float* val, int64_t rows, int64_t v, bool require_norm, int* hmax) {
-  if (ptr[0] != 0) return fail(c, LCEMD_E_BAD_CSR, "%s: rowptr[0] must be 0", what);
-  int hm = 0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const int64_t a = ptr[r], b = ptr[r + 1];
-    if (b <= a) return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld is empty or rowptr decreases", what, (long long)r);
-    if (b - a > LCEMD_MAX_HIST)
-      return fail(c, LCEMD_E_CAPACITY, "%s: row %lld has %lld non-zeros (limit %d)", what,
-                  (long long)r, (long long)(b - a), LCEMD_MAX_HIST);
-    hm = std::max<int>(hm, (int)(b - a));
-    double sum = 0.0;
-    int prev = -1;
-    for (int64_t i = a; i < b; ++i) {
-      if (col[i] <= prev || col[i] >= v)
-        return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld: column ids must be strictly increasing in [0, %lld)",
-                    what, (long long)r, (long long)v);
-      prev = col[i];
-      if (!(val[i] > 0.f) || !std::isfinite(val[i]))
-        return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld: weights must be finite and > 0", what, (long long)r);
-      sum += (double)val[i];
-    }
-    if (require_norm && std::fabs(sum - 1.0) > 1e-5)
-      return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld sums to %.9g, not 1", what, (long long)r, sum);
-  }
-  *hmax = hm;
-  return LCEMD_OK;
+  char msg[256];
+  const int rc = csr_check(what, ptr, col, val, rows, v, require_norm, hmax, msg, sizeof msg);
+  return rc ? fail(c, rc, "%s", msg) : LCEMD_OK;
 }
 
 int check_ptr_host(lcemd_ctx* c, const char* what, const int64_t* ptr, int64_t rows, int* hmax) {
-  if (ptr[0] != 0) return fail(c, LCEMD_E_BAD_CSR, "%s: rowptr[0] must be 0", what);
-  int hm = 0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const int64_t d = ptr[r + 1] - ptr[r];
-    if (d <= 0) return fail(c, LCEMD_E_BAD_CSR, "%s: row %lld is empty or rowptr decreases", what, (long long)r);
-    if (d > LCEMD_MAX_HIST)
-      return fail(c, LCEMD_E_CAPACITY, "%s: row %lld has %lld non-zeros (limit %d)", what,
-                  (long long)r, (long long)d, LCEMD_MAX_HIST);
-    hm = std::max<int>(hm, (int)d);
-  }
-  *hmax = hm;
-  return LCEMD_OK;
+  char msg[256];
+  const int rc = ptr_check(what, ptr, rows, hmax, msg, sizeof msg);
+  return rc ? fail(c, rc, "%s", msg) : LCEMD_OK;
 }
 
 // Device-resident query: validated and (for host input) staged on device.
