@@ -137,6 +137,12 @@ __device__ __forceinline__ uint32_t insert(uint32_t (&a)[LK], uint32_t c) {
 // Returns the cut entry (kNone if none).
 template <int LK, bool CAPSTOP>
 __device__ __forceinline__ uint32_t list_cut(const uint32_t (&a)[LK], const float* cap, int kef, float bound) {
+  // the capacities of the first entries are read together (one LDS round
+  // trip instead of one per entry); lists are cut within a few entries
+  constexpr int kPre = LK < 8 ? LK : 8;
+  float c[kPre];
+#pragma unroll
+  for (int i = 0; i < kPre; ++i) c[i] = (CAPSTOP && a[i] != kNone) ? cap[pk_pos(a[i])] : 0.f;
   float P = 0.f;
   uint32_t K0 = kNone;
 #pragma unroll
@@ -144,7 +150,7 @@ __device__ __forceinline__ uint32_t list_cut(const uint32_t (&a)[LK], const floa
     const bool live = K0 == kNone && a[i] != kNone;
     if (!__any(live)) break;
     if (live) {
-      P += cap[pk_pos(a[i])];
+      if (CAPSTOP) P += i < kPre ? c[i] : cap[pk_pos(a[i])];
       if (i + 1 >= kef || (CAPSTOP && P >= bound)) K0 = a[i];
     }
   }
