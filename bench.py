@@ -66,6 +66,9 @@ def phase1_kernel(method, k, precision, m):
     """The phase-1 kernel the library picks for the table (D2Q) pass of
     queries against m-dimensional embeddings."""
     depth = {"rwmd": 1, "omr": 2, "act": k, "ict": 64}[method]
+    mb = (m + 6 + 63) // 64 * 64
+    if precision == "bf16" and depth + 8 <= 32 and mb <= 384:  # its own kernel: P1_TABLE, list size, K steps
+        return f"k_phase1_bf16<0, {16 if depth + 8 <= 16 else 32}, {mb // 16}>"
     margin = 0 if precision == "fp32" or depth + 8 > 32 else 8
     kl = 2
     while kl < depth + margin:
@@ -96,7 +99,7 @@ def traffic_record(kernel, a, precision):
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    key = f"{a.workload}:{a.method}:{a.k}:{a.direction}:{precision}:{kernel.split('<')[0]}"
+    key = f"{a.workload}:{a.method}:{a.k}:{a.direction}:{precision}:{kernel}"
     e = rec.get(key)
     if not e or e.get("source_sha256") != digest:
         return None
@@ -118,7 +121,9 @@ def phase2_roofline(phases, steps, a, precision):
     if not p2 or p2["ms"] <= 0:
         return None
     ms = p2["ms"] / steps
-    recs = [traffic_record(k, a, precision) for k in ("k_p2_word_costs", "k_p2_doc_sums")]
+    kt = {"rwmd": 1, "omr": 2, "act": a.k}.get(a.method, 64)
+    recs = [traffic_record(k, a, precision) for k in (f"k_p2_word_costs<{4 if (kt + 1) // 2 <= 4 else 8}>",
+                                                      "k_p2_doc_sums")]
     out = {"bound": "hbm", "ms_per_step": ms, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
            "a2_algorithmic_GBps": p2["work"] / (p2["ms"] * 1e-3) / 1e9}
     if all(recs):
@@ -577,7 +582,7 @@ def roofline_of(phases, precision, a):
         flops = p1["work"] / max(1, p1["launches"])
         ach = flops / (ms * 1e-3) if ms > 0 else 0.0
         peak = PEAKS.get(precision, PEAKS["fp32"])
-        kernel = "k_phase1_bf16" if precision == "bf16" else phase1_kernel(a.method, a.k, precision, 300)
+        kernel = phase1_kernel(a.method, a.k, precision, a.m)
         return {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": ach / peak,
                 "traffic": measured_traffic(kernel, a, precision), "kernel": kernel, "avg_launch_ms": ms,
                 "flops_per_launch": flops}
@@ -609,6 +614,7 @@ def main():
         kw["B"] = a.B
     t0 = time.time()
     w = make_workload(a.workload, **kw)
+    a.m = int(w.V.shape[1])
     print(f"[bench] {a.workload} workload built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     # the CPU baseline runs first, in forked workers, before any GPU work
     full = a.workload == "text-1M" and not kw
