@@ -196,8 +196,9 @@ int lcemd_topl(lcemd_ctx* ctx, const lcemd_query* q, const lcemd_opts* o,
  * call itself allocates nothing, host or device.  Restrictions:
  * LCEMD_PTR_DEVICE (queries and outputs in device memory), direction D2Q,
  * 1..4096 queries of at most 512 words, B x n distances within half the
- * region (LCEMD_E_CAPACITY otherwise, or when the tables of one query do not
- * fit what is left); bf16 / fp8 keys need their copy built at load
+ * region, and one query's tables (512 x ceil(KT / 2) bytes per used
+ * vocabulary word: about 260,000 words at k <= 2, 65,000 at k = 8) within
+ * what is left (LCEMD_E_CAPACITY otherwise); bf16 / fp8 keys need their copy built at load
  * (LCEMD_MAKE_BF16 / LCEMD_MAKE_FP8), else LCEMD_E_UNSUPPORTED.  Results
  * equal lcemd_topl's (same kernels).  Every call on a GPU shares that GPU's
  * region and leaves its contents behind (what must start at zero is cleared

@@ -194,13 +194,16 @@ def test_unknown_load_flags_rejected(L):
     assert np.array_equal(before, after)
 
 
+MEASURES_WM = [("act", 3), ("act", 8), ("act", 16), ("rwmd", 1), ("omr", 1)]
+
+
 def test_word_major_phase2_matches_per_document(L, monkeypatch):
     """Phase 2 word-major (forced here; chosen by itself when a query
     group's tables outgrow the caches): 150 queries -- two whole 64-query
     groups word-major, a 22-query tail per document -- against 300
     documents, ACT k = 3, 8 and 16 (one, four and eight table pairs per
-    float4 run) and RWMD: bit for bit the per-document kernel's distances,
-    and the oracle's."""
+    float4 run), RWMD and OMR: bit for bit the per-document kernel's
+    distances, and the oracle's."""
     from synth import make_workload
 
     w = make_workload("text", n=300, B=150, v=3000)
@@ -210,11 +213,11 @@ def test_word_major_phase2_matches_per_document(L, monkeypatch):
     for mode in ("1", "2"):
         monkeypatch.setenv("LCEMD_PHASE2", mode)
         ctx = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val)
-        for method, k in (("act", 3), ("act", 8), ("act", 16), ("rwmd", 1)):
+        for method, k in MEASURES_WM:
             say(f"[gpu] phase-2 mode {mode}: 150 x 300 {method} k={k} d2q")
             got[mode, method, k] = ctx.distances(q.rowptr, q.col, q.val, method=method, k=k, direction="d2q")
         ctx.close()
-    for method, k in (("act", 3), ("act", 8), ("act", 16), ("rwmd", 1)):
+    for method, k in MEASURES_WM:
         assert np.array_equal(got["1", method, k], got["2", method, k]), (method, k)
     sel = [0, 1, 63, 64, 100, 127, 128, 149]
     s = q.take(sel)

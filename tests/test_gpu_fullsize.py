@@ -171,6 +171,49 @@ def test_text_1m_word_major_phase2(L, monkeypatch):
         P.assert_distances(np.array([float(d[int(b), int(u)])]), np.array([o]), f"query {b} doc {u}")
 
 
+def test_text_1m_serving_and_noalloc(L):
+    """The serving path and the allocation-free call at the 1M-document
+    size: queries of the arrival trace (10-500 words) served in one batch on
+    one lane (the 8-lane phase-2 kernel of its live-count band) and on
+    three, equal bit for bit to lcemd_topl on each query alone; and
+    lcemd_topl_noalloc, whose 256 MiB region cannot hold one query's tables
+    over a million used words (512 bytes per word and table pair run, 2 GB
+    here), refusing with LCEMD_E_CAPACITY and leaving the context usable."""
+    import torch
+
+    from synth import arrival_trace
+
+    w = make_workload("text-1M", B=24)
+    say("[gpu] 1M-word serving and allocation-free calls")
+    ctx = L.open_context(w.V, w.db.rowptr, w.db.col, w.db.val, precisions=("bf16",))
+    _, qs = arrival_trace(1000.0, 7, w.V.shape[0], lmin=10, lmax=500)
+    ref = []
+    for b in range(qs.n):
+        one = qs.take([b])
+        i, d = ctx.topl(one.rowptr, one.col, one.val, 16, method="act", k=8, direction="sym", precision="bf16")
+        ref.append((i[0], d[0]))
+    for lanes in (1, 3):
+        srv = L.Server(ctx, method="act", k=8, precision="bf16", l=16, max_slots=8, lanes=lanes)
+        try:
+            got = [srv.wait(t) for t in [srv.submit(*qs.row(b)) for b in range(qs.n)]]
+        finally:
+            srv.stop()
+        for b, (i, d, _) in enumerate(got):
+            assert np.array_equal(i, ref[b][0]) and np.array_equal(d, ref[b][1]), (lanes, b)
+    dev = torch.device("cuda:0")
+    s = w.queries.take([3, 9, 17])
+    q = [torch.from_numpy(x).to(dev) for x in (s.rowptr, s.col, s.val)]
+    out = (torch.full((s.n, 16), -1, dtype=torch.int64, device=dev),
+           torch.full((s.n, 16), -1.0, dtype=torch.float32, device=dev))
+    with pytest.raises(L.LcemdError) as e:
+        ctx.topl_noalloc(*q, 16, out, method="act", k=8, precision="bf16")
+    assert e.value.code == L.E_CAPACITY and "allocation-free" in str(e.value)
+    r = ctx.topl(*q, 16, method="act", k=8, direction="d2q", precision="bf16")
+    i0, d0 = ctx.topl(s.rowptr, s.col, s.val, 16, method="act", k=8, direction="d2q", precision="bf16")
+    assert np.array_equal(r[0].cpu().numpy(), i0) and np.array_equal(r[1].cpu().numpy(), d0)
+    ctx.close()
+
+
 def certified_row(orc, qc, qw, method, k, tau, tol_frac=1e-5):
     """The oracle's symmetric distances of one query against the whole
     database wherever they can reach the top-l: every document whose
