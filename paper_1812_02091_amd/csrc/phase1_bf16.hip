@@ -62,7 +62,7 @@ constexpr int kBKS = kBMaxMb / 16;    // K steps held in registers
 constexpr int kBQa = 2 * kBMaxMb + 16; // bytes per staged word (16 bytes of padding)
 constexpr int kBSeg = kSegShort;      // query words per item
 constexpr int kBStg = 34;             // u32 per row: candidate staging [2][17] / final list
-constexpr int kBGroup = 8;            // queries per item group (query-fastest)
+constexpr int kBGroup = 32;           // queries per item group (query-fastest): a row block stays in L2 for 32 items
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr uint32_t kPosMask = 511u;   // 9 position bits (words < 512)
 // twice the largest relative rounding of a packed key: 2 * 2^(9 - 23)
