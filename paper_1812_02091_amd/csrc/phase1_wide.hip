@@ -48,11 +48,14 @@ constexpr int kCK = 66;         // floats per key row (64 columns + 2 pad)
 constexpr int kQSCap = kWR * kCK;  // floats of the staging area (the key buffer's size)
 constexpr int kSeg = kSegShort;            // segment words held in LDS (short variant)
 constexpr int kSegLong = LCEMD_MAX_HIST;   // long variant (float32 keys)
-// queries per tile group (table modes): 8, or 32 for vocabularies of at
-// least 2^18 used words, where a row block's vectors are reused by more
-// items before they leave L2 (1M words: phase 1 -5.5 %; 70,000 words: 8
-// keeps a group's query vectors within an XCD's L2)
-__host__ __device__ inline int wide_group_log2(int64_t v_used) { return v_used >= (int64_t(1) << 18) ? 5 : 3; }
+// queries per tile group (table modes): 8, or 32 with float32 keys over
+// vocabularies of at least 2^18 used words, where a row block's vectors are
+// reused by more items before they leave L2 (1M words: phase 1 -2 %; with
+// fp8 keys 32 was 3 % slower; 70,000 words: 8 keeps a group's query vectors
+// within an XCD's L2)
+__host__ __device__ inline int wide_group_log2(int64_t v_used, int prec) {
+  return prec == PREC_F32 && v_used >= (int64_t(1) << 18) ? 5 : 3;
+}
 constexpr float kGuardW = 0.25f;
 constexpr float kBandBF16 = 0.015625f * 1.07f;  // 2^-6 * 1.07
 // fp8 (e4m3, 3 mantissa bits): a statistical band, not a worst-case one --
@@ -352,7 +355,7 @@ __device__ __forceinline__ void wide_task(const P1Args& a, unsigned char* smem_r
     // query vectors and a row block's vectors in its L2
     const int64_t nrb = (a.v_used + kWR - 1) / kWR;
     const int64_t work = item;
-    const int lg = wide_group_log2(a.v_used);
+    const int lg = wide_group_log2(a.v_used, PREC);
     const int64_t qin = work & ((int64_t(1) << lg) - 1), t = work >> lg;
     const int64_t rblk = t % nrb, g = t / nrb;
     const int64_t qi = (g << lg) + qin;
@@ -830,7 +833,7 @@ static hipError_t launch_wide_one(const P1Args& a, hipStream_t s) {
     total = a.npairs * (int64_t)a.rb_max;
   } else {
     const int64_t nrb = (a.v_used + kWR - 1) / kWR;
-    const int64_t gw = int64_t(1) << wide_group_log2(a.v_used);
+    const int64_t gw = int64_t(1) << wide_group_log2(a.v_used, PREC);
     total = (a.nq + gw - 1) / gw * nrb * gw;
   }
   if (total <= 0) return hipSuccess;
