@@ -277,8 +277,10 @@ int lcemd_profile_get(lcemd_ctx* ctx, lcemd_phase_time* out, int cap);
  * batches add no throughput and lengthen each other; with one lane the
  * next batch starts the moment the previous one ends, with every query
  * that arrived meanwhile.  A batch runs phase 1
- * tables, the exact redo of uncertified rows, phase 2 on a persistent
- * kernel fed by per-XCD work counters, D2Q candidate selection, Q2D of the
+ * tables, the exact redo of uncertified rows, phase 2 on persistent
+ * kernels fed by per-XCD work counters (one per query-lane width; the one
+ * whose band holds the live query count does the work), D2Q candidate
+ * selection, Q2D of the
  * candidates and the symmetric top-l, and completes each query
  * independently.  A query whose top-l certificate fails, or whose lists
  * overflowed, is finished by lcemd_topl.  lcemd_serve_sim runs the same
