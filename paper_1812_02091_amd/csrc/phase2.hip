@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_phase2_persistent(
   while (true) {
     unsigned long long it = 0;
     if (lane == 0) it = atomicAdd(&counters[xcd], 1ull);
-    const int64_t item = lo + (int64_t)__shfl((long long)it, 0);
+    const int64_t item = uniform64(lo + (int64_t)__shfl((long long)it, 0));
     if (item >= hi) break;
     // lanes past the batch walk the last query's table (so every lane of a
     // document group takes part in its record shuffles) and write nothing
@@ -325,7 +325,9 @@ __global__ __launch_bounds__(kThreads) void k_p2_word_costs(
     const int64_t* __restrict__ wptr, const float* __restrict__ wwt, int64_t nnz, int64_t v_used,
     const float4* __restrict__ ZP, int64_t zw_nq, int KP, float* __restrict__ cost) {
   const int lane = threadIdx.x & 63;
-  const int64_t gw = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  // the wave's index, made visibly wave-uniform (its range, offsets and
+  // counts then live in scalar registers)
+  const int64_t gw = (int64_t)blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t e0 = gw * kWmSpan, e1 = min(nnz, e0 + kWmSpan);
   if (e0 >= e1) return;
   // the word of e0: the last p with wptr[p] <= e0 (wave-uniform search)
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(kThreads) void k_p2_word_costs(
       bool any = false;
 #pragma unroll
       for (int k = 0; k < kUnroll; ++k) {
-        rem[k] = k < cnt ? rec[k] : 0.f;
+        rem[k] = rec[k];  // 0 past the range: the weight blocks hold 0 there
         acc[k] = 0.f;
         step(rem[k], acc[k], f[0].x, f[0].y);
         if (rem[k] > 0.f) step(rem[k], acc[k], f[0].z, f[0].w);
@@ -394,9 +396,14 @@ __global__ __launch_bounds__(kThreads) void k_p2_word_costs(
           }
         }
       }
+      if (cnt == kUnroll) {
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k)
-        if (k < cnt) cb[k * 64] = acc[k];
+        for (int k = 0; k < kUnroll; ++k) cb[k * 64] = acc[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k)
+          if (k < cnt) cb[k * 64] = acc[k];
+      }
       continue;
     }
     // the batch crosses into later words: one walk at a time
@@ -457,7 +464,7 @@ __global__ __launch_bounds__(kThreads) void k_p2_doc_sums(const int64_t* __restr
   while (true) {
     unsigned long long it = 0;
     if (lane == 0) it = atomicAdd(&counters[8 + xcd], 1ull);
-    const int64_t item = lo + (int64_t)__shfl((long long)it, 0);
+    const int64_t item = uniform64(lo + (int64_t)__shfl((long long)it, 0));
     if (item >= hi) break;
     const int64_t d0 = item * kItemSlots;
     int cnt = 0;
