@@ -274,6 +274,9 @@ __global__ __launch_bounds__(kThreads) void k_phase1_f32(P1Args a) {
           const int64_t flat = out_row0 + row;
           float2* pr = (float2*)zw_pair(a.ZW, a.zw_nq, a.KT, flat / a.v_used, flat % a.v_used, (depth - 1) >> 1);
           pr[(depth - 1) & 1] = make_float2(z, (stop || ovf) ? INFINITY : w);
+          // a row's last pair is written whole (phase 2 steps the second
+          // entry of the first pair without testing the remaining mass)
+          if ((stop || ovf) && ((depth - 1) & 1) == 0) pr[1] = make_float2(0.f, 0.f);
           if (ovf) a.overflow[0] = 1;
         }
         stop = stop || ovf;

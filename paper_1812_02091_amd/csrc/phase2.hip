@@ -34,7 +34,12 @@ static_assert(kItemSlots % 4 == 0, "results are stored four at a time");
 // One transfer step of Eq. (6)-(8) against table entry (z, w).  rem >= +0
 // (never -0: rem - rem is +0) and w > 0 (or +inf), so the smaller float is
 // the smaller bit pattern: one integer minimum (fminf would first
-// canonicalise both operands).
+// canonicalise both operands).  A step with rem = +0 changes nothing
+// (r = +0, acc + 0 z = acc for finite z >= 0): so the second entry of a
+// table row's first 16-byte pair, which is always written (as (0, 0) when
+// the row has one entry), is stepped without testing rem; later pairs are
+// read only while some mass remains (their entries past the row's sink are
+// never written).
 __device__ __forceinline__ void step(float& rem, float& acc, float z, float w) {
   const float r = __uint_as_float(min(__float_as_uint(rem), __float_as_uint(w)));
   rem -= r;
@@ -108,7 +113,7 @@ __device__ __forceinline__ float doc_cost(int64_t e0, int64_t e1, const int2* __
       rem[k] = __int_as_float(cv[k].y);  // 0 for the padding slots
       acc[k] = 0.f;
       step(rem[k], acc[k], f[k].x, f[k].y);
-      if (rem[k] > 0.f) step(rem[k], acc[k], f[k].z, f[k].w);
+      step(rem[k], acc[k], f[k].z, f[k].w);
       any = any || rem[k] > 0.f;
     }
     for (int p = 1; any && p < KP; ++p) {
@@ -376,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void k_p2_word_costs(
         rem[k] = rec[k];  // 0 past the range: the weight blocks hold 0 there
         acc[k] = 0.f;
         step(rem[k], acc[k], f[0].x, f[0].y);
-        if (rem[k] > 0.f) step(rem[k], acc[k], f[0].z, f[0].w);
+        step(rem[k], acc[k], f[0].z, f[0].w);
         any = any || rem[k] > 0.f;
       }
 #pragma unroll
@@ -432,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_p2_word_costs(
       }
       float rem = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wcur0), off + k)), acc = 0.f;
       step(rem, acc, f[0].x, f[0].y);
-      if (rem > 0.f) step(rem, acc, f[0].z, f[0].w);
+      step(rem, acc, f[0].z, f[0].w);
 #pragma unroll
       for (int p = 1; p < KPM; ++p) {
         if (p >= KP || !__any(rem > 0.f)) break;
