@@ -312,6 +312,10 @@ int p1_launch(lcemd_ctx* c, P1Args& a, int mode, int prec, int depth, int seg_hm
       int rc = wsget(c, "bf16_qinfo", (size_t)std::max<int64_t>(a.qnnz, 1), a.qinfo);
       if (rc) return rc;
     }
+    if (!a.qmx) {
+      int rc = wsget(c, "bf16_qmax", (size_t)std::max<int64_t>(a.nq, 1), a.qmx);
+      if (rc) return rc;
+    }
     HIPCHK(c, launch_phase1_bf16(a, mode, depth, c->stream));
     return LCEMD_OK;
   }

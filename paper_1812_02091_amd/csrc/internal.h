@@ -60,6 +60,7 @@ struct P1Args {
   const float* vres;      // [v] |v - bf16(v)|, rounded up (bf16 error bound)
   float4* rinfo;          // bf16 kernel scratch: [v_used] row records
   float4* qinfo;          // bf16 kernel scratch: [qnnz] query-word records
+  float2* qmx;            // bf16 kernel scratch: [nq] per query (max |q|^2, max |q - bf16(q)|)
   int64_t qnnz;           // query non-zeros (qptr[B]) the records cover
   int mb;                 // dims per bfloat16 row (bf16_row_dims(m))
   int m;                  // real dims

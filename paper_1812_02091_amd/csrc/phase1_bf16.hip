@@ -306,30 +306,17 @@ __device__ __forceinline__ void bf16_task(const P1Args& a, BfSmem& sm, int64_t i
     sm.reps[tid] = ri.w;  // |e_v|, replaced by the row's eps below
     sm.rflag[tid] = 0;
   }
-  float mq = 0.f, me = 0.f;
   for (int c = tid; c < h; c += kBT) {
     const float4 qi = a.qinfo[s0 + c];
     sm.cid[c] = __float_as_int(qi.x);
     sm.cap[c] = qi.y;
     sm.qn[c] = qi.z;
-    mq = fmaxf(mq, qi.z);
-    me = fmaxf(me, qi.w);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    mq = fmaxf(mq, __shfl_xor(mq, o));
-    me = fmaxf(me, __shfl_xor(me, o));
+  if (tid == 0) {  // the query's largest |q|^2 and |q - bf16(q)| (k_bf16_qmax)
+    const float2 mx = a.qmx[qi];
+    sm.qmax = sqrtf(mx.x) * 1.0001f;
+    sm.eqmax = mx.y;
   }
-  if (tid == 0) {
-    sm.qmax = 0.f;
-    sm.eqmax = 0.f;
-  }
-  __syncthreads();
-  if ((tid & 63) == 0) {  // float maxima of non-negative values: as integers
-    atomicMax((int*)&sm.qmax, __float_as_int(mq));
-    atomicMax((int*)&sm.eqmax, __float_as_int(me));
-  }
-  __syncthreads();
-  if (tid == 0) sm.qmax = sqrtf(sm.qmax) * 1.0001f;
   __syncthreads();
   if (tid < kBR) {
     const float nv = sqrtf(sm.rvn[tid]) * 1.0001f, qm = sm.qmax;
@@ -647,6 +634,26 @@ __global__ __launch_bounds__(kThreads) void k_bf16_info(P1Args a) {
   }
 }
 
+// Per query of the launch, the largest |q|^2 and |q - bf16(q)| over its
+// words (from qinfo): one wave per query.
+__global__ __launch_bounds__(kThreads) void k_bf16_qmax(P1Args a) {
+  const int64_t qi = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (qi >= a.nq) return;
+  const int64_t s0 = a.qptr[a.q0 + qi], s1 = a.qptr[a.q0 + qi + 1];
+  float mq = 0.f, me = 0.f;
+  for (int64_t j = s0 + lane; j < s1; j += 64) {
+    const float4 q = a.qinfo[j];
+    mq = fmaxf(mq, q.z);
+    me = fmaxf(me, q.w);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mq = fmaxf(mq, __shfl_xor(mq, o));
+    me = fmaxf(me, __shfl_xor(me, o));
+  }
+  if (lane == 0) a.qmx[qi] = make_float2(mq, me);
+}
+
 }  // namespace
 
 bool phase1_bf16_fits(int mb, int seg_hmax, int depth) {
@@ -667,15 +674,21 @@ hipError_t launch_bf16_width(const P1Args& a, hipStream_t s) {
 }
 
 hipError_t launch_phase1_bf16(const P1Args& a, int mode, int depth, hipStream_t s) {
-  if (!a.Vb || !a.Vbq || !a.vres || !a.rinfo || !a.qinfo || a.mb % 64 != 0 || a.mb > kBMaxMb || a.mb < a.m + 6)
+  if (!a.Vb || !a.Vbq || !a.vres || !a.rinfo || !a.qinfo || !a.qmx || a.mb % 64 != 0 || a.mb > kBMaxMb ||
+      a.mb < a.m + 6)
     return hipErrorInvalidValue;
   {
     // grid-stride over the rows and the launch's query words (at most qnnz)
     const int64_t n = std::max<int64_t>(a.v_used, a.qnnz);
     const unsigned g = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 8192);
     hipLaunchKernelGGL(k_bf16_info, dim3(g), dim3(kThreads), 0, s, a);
-    const hipError_t e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (a.nq > 0) {
+      hipLaunchKernelGGL(k_bf16_qmax, dim3((unsigned)((a.nq + kThreads / 64 - 1) / (kThreads / 64))), dim3(kThreads),
+                         0, s, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   const bool small = depth + 8 <= 16;
   if (mode == P1_TABLE) return small ? launch_bf16_width<P1_TABLE, 16>(a, s) : launch_bf16_width<P1_TABLE, 32>(a, s);

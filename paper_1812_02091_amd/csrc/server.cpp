@@ -77,6 +77,7 @@ struct Lane {
   float* partial = nullptr;
   float4* rinfo = nullptr;  // bf16 phase-1 records (lane-owned: graphs capture the pointers)
   float4* qinfo = nullptr;
+  float2* qmx = nullptr;
   int64_t* idx = nullptr;
   float* dist = nullptr;
   int* flags = nullptr;
@@ -140,7 +141,7 @@ int halloc(lcemd_ctx* c, T*& p, size_t count) {
 
 void free_lane(Lane& L) {
   if (L.gexec) (void)hipGraphExecDestroy(L.gexec);
-  void* dev[] = {L.qptr, L.qcol, L.qval, L.nq, L.ints, L.ctr, L.fixl, L.ZW, L.d2q, L.cand, L.seltmp, L.q2dv, L.partial, L.rinfo, L.qinfo, L.idx, L.dist, L.flags};
+  void* dev[] = {L.qptr, L.qcol, L.qval, L.nq, L.ints, L.ctr, L.fixl, L.ZW, L.d2q, L.cand, L.seltmp, L.q2dv, L.partial, L.rinfo, L.qinfo, L.qmx, L.idx, L.dist, L.flags};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {L.h_qptr, L.h_qcol, L.h_qval, L.h_nq, L.h_idx, L.h_dist, L.h_flags, L.h_ints};
@@ -195,6 +196,7 @@ int issue(lcemd_server* s, Lane& L) {
     a.fix_cap = kFixCapLane;
     a.rinfo = L.rinfo;
     a.qinfo = L.qinfo;
+    a.qmx = L.qmx;
     a.qnnz = s->W;  // the lane's word capacity (padding words are never read)
     // ICT lists stop at 16 entries as in lcemd_topl; deeper rows go to the
     // exact redo below (tables hold s->KT entries)
@@ -238,6 +240,7 @@ int setup_lane(lcemd_server* s, Lane& L) {
       (rc = dalloc(c, L.q2dv, B * s->use, "lane")) ||
       (rc = dalloc(c, L.partial, B * s->use * rbcap, "lane")) ||
       (rc = dalloc(c, L.rinfo, c->v_used, "lane")) || (rc = dalloc(c, L.qinfo, W, "lane")) ||
+      (rc = dalloc(c, L.qmx, B, "lane")) ||
       (rc = dalloc(c, L.idx, B * s->l, "lane")) || (rc = dalloc(c, L.dist, B * s->l, "lane")) ||
       (rc = dalloc(c, L.flags, B, "lane")))
     return rc;
