@@ -239,21 +239,24 @@ __device__ __forceinline__ void recompute(const P1Args& a, BfSmem& sm, int h, in
     __syncthreads();
     if (ch + 1 < nch) fetch(d0 + RD);  // in flight during this chunk's products
     float4 qv[Q];
+    // fully unrolled (entries skipped by a wave-uniform test, not a loop
+    // exit), so pos[] and dot[] stay in fixed registers
 #pragma unroll
     for (int e = 0; e < LK; ++e) {
-      if (e >= wlen) break;
-      const float* qp = &sm.u.qf[pos[e] * RS + sub * HALF];
+      if (e < wlen) {
+        const float* qp = &sm.u.qf[pos[e] * RS + sub * HALF];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) qv[q] = *(const float4*)(qp + 4 * q);
-      float t = dot[e];
+        for (int q = 0; q < Q; ++q) qv[q] = *(const float4*)(qp + 4 * q);
+        float t = dot[e];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        t = fmaf(vc[q].x, qv[q].x, t);
-        t = fmaf(vc[q].y, qv[q].y, t);
-        t = fmaf(vc[q].z, qv[q].z, t);
-        t = fmaf(vc[q].w, qv[q].w, t);
+        for (int q = 0; q < Q; ++q) {
+          t = fmaf(vc[q].x, qv[q].x, t);
+          t = fmaf(vc[q].y, qv[q].y, t);
+          t = fmaf(vc[q].z, qv[q].z, t);
+          t = fmaf(vc[q].w, qv[q].w, t);
+        }
+        dot[e] = t;
       }
-      dot[e] = t;
     }
   }
   __syncthreads();  // the staged vectors are dead: zb may reuse their LDS
