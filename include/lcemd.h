@@ -257,8 +257,9 @@ int lcemd_profile(lcemd_ctx* ctx, int enable);
 /* Cumulative counts since lcemd_create: query tiles whose phase 1 was redone
  * with float32 keys or deeper lists (a row needed more candidates than the
  * fast kernels keep), and bfloat16 table rows whose exactness certificate
- * failed and that were redone one by one with float32 distances.  Either
- * pointer may be NULL. */
+ * failed and that were redone one by one with float32 distances (counted on
+ * the device: reading it waits for the context's stream).  Either pointer
+ * may be NULL. */
 int lcemd_counters(lcemd_ctx* ctx, int64_t* fallback_tiles, int64_t* exact_rows);
 int lcemd_profile_get(lcemd_ctx* ctx, lcemd_phase_time* out, int cap);
 

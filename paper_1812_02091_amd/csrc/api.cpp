@@ -235,6 +235,7 @@ int check_opts(lcemd_ctx* c, const lcemd_opts* o) {
 constexpr int kMargin = 8;  // over-selection for approximate (bf16/fp8) keys
 constexpr int kFixCap = 1 << 23;  // rows per launch that may be redone exactly (64 MB list)
 constexpr int kFixCapNoAlloc = 1 << 16;  // the same in allocation-free calls
+constexpr int kFixGrid = 4096;  // rows the exact-redo launch sizes its grid for (it strides over more)
 constexpr int kNoAllocMaxQueries = 4096;   // queries per allocation-free call
 
 int pow2ceil(int x) {
@@ -441,103 +442,139 @@ P1Args base_args(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts
 
 P1Args base_args(lcemd_ctx* c, const QDev& Q, const lcemd_opts* o) { return base_args(c, db_view(c), Q, o); }
 
+// Queries per table tile at list depth KT: the tables stay under the
+// context's budget, or (allocation-free) half of what the scratch region
+// has left.
+int64_t d2q_tile_queries(lcemd_ctx* c, const DbView& db, int KT) {
+  const size_t per_q = (size_t)db.v_used * sizeof(float2);
+  const size_t tbudget = c->arena.base ? (c->arena.cap - std::min(c->arena.cap, c->arena.used)) / 2 : c->table_budget;
+  int64_t Bt = (int64_t)std::max<size_t>(1, tbudget / (per_q * 2 * zw_pairs(KT)));
+  Bt = std::min<int64_t>(Bt, 16384);  // also bounds the rows a tile may need to redo
+  // whole 64-query groups per tile: phase 2 runs a wave per 64 queries of
+  // a document, so a tile of 64 g + r queries pays a full group for r
+  if (Bt >= 64) Bt = Bt / 64 * 64;
+  return Bt;
+}
+
+// One table tile, queries [q0, q0 + nq): phase 1 (Alg. 2-3 tables), the
+// exact redo of the rows it could not certify, and phase 2 (Eq. (6)-(9))
+// into out.  Nothing is read back: a row deeper than the lists raises *ovf
+// on the device, and the caller then runs the tile again.
+int d2q_tile(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, int64_t q0, int64_t nq,
+             int prec, bool full_lists, int KT, int* ovf, float* out, int64_t ld) {
+  int rc;
+  float2* ZW;
+  if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * db.v_used * 2 * zw_pairs(KT), ZW))) return rc;
+  P1Args a = base_args(c, db, Q, o);
+  a.qnnz = Q.nnz;
+  a.KT = KT;
+  a.q0 = q0;
+  a.nq = nq;
+  a.ZW = ZW;
+  a.zw_nq = zw_pitch(nq);
+  a.overflow = ovf;
+  // rows whose quantised selection is not certified are listed for an
+  // exact redo (every precision on the 128-row kernel); the redo kernel
+  // reads the listed count on the device
+  int* fixc = nullptr;
+  const int fixcap = c->arena.base ? kFixCapNoAlloc : kFixCap;
+  if ((rc = wsget(c, "fix_count", 1, fixc)) || (rc = wsget(c, "fix_list", fixcap, a.fix_list))) return rc;
+  HIPCHK(c, launch_zero_ints(fixc, 1, c->stream));
+  a.fix_count = fixc;
+  a.fix_cap = fixcap;
+  a.fix_total = c->fix_total;
+  const int64_t H = Q.hptr.empty() ? Q.nnz : Q.hptr[q0 + nq] - Q.hptr[q0];
+  if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)db.v_used * (double)H * (double)c->m))) return rc;
+  const int list_depth = full_lists ? KT : std::min(KT, kIctList);
+  if ((rc = p1_launch(c, a, P1_TABLE, prec, list_depth, Q.hmax, Q.hmax))) return rc;
+  if ((rc = prof_end(c))) return rc;
+  if ((rc = prof_begin(c, "fix_rows", 0.0))) return rc;
+  HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixGrid, c->stream));
+  if ((rc = prof_end(c))) return rc;
+  const double a2 = (double)nq * (8.0 * db.nnz + 8.0 * (db.n + 1) + 8.0 * (double)db.v_used * KT + 4.0 * db.n);
+  if ((rc = prof_begin(c, "phase2", a2))) return rc;
+  unsigned long long* p2c;
+  if ((rc = wsget(c, "p2_counters", 16, p2c))) return rc;
+  // whole 64-query groups word-major where that pays, the rest (and every
+  // group otherwise) per document; both give the same bits
+  const int64_t ng = !c->arena.base && use_word_major(c, db, KT) ? nq / 64 : 0;
+  if (ng > 0) {
+    float* cost;
+    if ((rc = wsget(c, "p2_cost", (size_t)db.nnz * 64, cost))) return rc;
+    for (int64_t g = 0; g < ng; ++g)
+      HIPCHK(c, launch_phase2_wordmajor(db.xptr, db.n, db.wptr, db.wwt, db.winv, db.nnz, db.v_used,
+                                        ZW + 2 * 64 * g, a.zw_nq, KT, cost, out + (q0 + 64 * g) * ld, ld, p2c,
+                                        c->stream));
+  }
+  if (nq > 64 * ng)
+    HIPCHK(c, launch_phase2_persistent(db.xptr, db.xcv, db.n, db.perm, ZW + 2 * 64 * ng, a.zw_nq, KT, nq - 64 * ng,
+                                       nullptr, out + (q0 + 64 * ng) * ld, ld, p2c, c->stream));
+  if ((rc = prof_end(c))) return rc;
+  return LCEMD_OK;
+}
+
 // D2Q distances of every query against every row of `db` (Sec. 4):
-// out[b * ld + u].
+// out[b * ld + u].  The tiles run back to back, each with its own overflow
+// flag; the flags are read once, after the last tile, and a tile that
+// overflowed is run again with float32 keys, then (ICT) with full-depth
+// lists.  Phase 2 of an overflowed tile reads incomplete tables, but its
+// loops are bounded by the list depth, and the rerun overwrites its rows.
 int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
-  int KT = table_depth(o, Q.hmax);
+  const int KT0 = table_depth(o, Q.hmax);
   // ICT: the tables hold up to KT entries per row, but the lists of phase 1
   // stop at kIctList (a row needs a few entries before its capacities cover
   // the word's largest weight, Lemma 1); deeper rows are redone exactly
-  bool full_lists = o->method != LCEMD_ICT;
-  int prec = o->precision;
-  const size_t per_q = (size_t)db.v_used * sizeof(float2);
+  const bool full0 = o->method != LCEMD_ICT;
+  if (Q.B < 1) return LCEMD_OK;
   int* ovf;
   int rc;
-  if ((rc = wsget(c, "ovf", 1, ovf))) return rc;
-  int64_t q0 = 0;
-  while (q0 < Q.B) {
-    // tables: under the context's budget, or (allocation-free) half of what
-    // the scratch region has left
-    const size_t tbudget = c->arena.base ? (c->arena.cap - std::min(c->arena.cap, c->arena.used)) / 2 : c->table_budget;
-    int64_t Bt = (int64_t)std::max<size_t>(1, tbudget / (per_q * 2 * zw_pairs(KT)));
-    Bt = std::min<int64_t>(Bt, 16384);  // also bounds the rows a tile may need to redo
-    // whole 64-query groups per tile: phase 2 runs a wave per 64 queries of
-    // a document, so a tile of 64 g + r queries pays a full group for r
-    if (Bt >= 64) Bt = Bt / 64 * 64;
-    const int64_t nq = std::min<int64_t>(Bt, Q.B - q0);
-    float2* ZW;
-    if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * db.v_used * 2 * zw_pairs(KT), ZW))) return rc;
-    HIPCHK(c, launch_zero_ints(ovf, 1, c->stream));
-    P1Args a = base_args(c, db, Q, o);
-    a.qnnz = Q.nnz;
-    a.KT = KT;
-    a.q0 = q0;
-    a.nq = nq;
-    a.ZW = ZW;
-    a.zw_nq = zw_pitch(nq);
-    a.overflow = ovf;
-    // rows whose quantised selection is not certified are listed for an
-    // exact redo (every precision on the 128-row kernel)
-    int* fixc = nullptr;
-    const int fixcap = c->arena.base ? kFixCapNoAlloc : kFixCap;
-    if ((rc = wsget(c, "fix_count", 1, fixc)) || (rc = wsget(c, "fix_list", fixcap, a.fix_list))) return rc;
-    HIPCHK(c, launch_zero_ints(fixc, 1, c->stream));
-    a.fix_count = fixc;
-    a.fix_cap = fixcap;
-    const int64_t H = Q.hptr.empty() ? Q.nnz : Q.hptr[q0 + nq] - Q.hptr[q0];
-    if ((rc = prof_begin(c, "phase1_table", 2.0 * (double)db.v_used * (double)H * (double)c->m))) return rc;
-    const int list_depth = full_lists ? KT : std::min(KT, kIctList);
-    if ((rc = p1_launch(c, a, P1_TABLE, prec, list_depth, Q.hmax, Q.hmax))) return rc;
-    if ((rc = prof_end(c))) return rc;
-    {
-      int h_ovf = 0, h_fix = 0;
-      HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      if (fixc) HIPCHK(c, hipMemcpyAsync(&h_fix, fixc, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      if (!h_ovf && h_fix > 0) {
-        if ((rc = prof_begin(c, "fix_rows", (double)h_fix))) return rc;
-        HIPCHK(c, launch_fix_rows(a, P1_TABLE, h_fix, c->stream));
-        if ((rc = prof_end(c))) return rc;
-        c->fixed_rows += h_fix;
-        HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-      }
-      if (h_ovf) {
-        // a row needed more list entries than the kernel keeps: redo the tile
-        // with float32 keys, and for ICT with full-depth tables
-        ++c->fallbacks;
-        if (prec != LCEMD_FP32) {
-          prec = LCEMD_FP32;
-        } else {
-          // the exact redo of ICT's short lists already reaches KT entries:
-          // an overflow there needs the full depth
-          full_lists = true;
-          KT = Q.hmax;
-        }
-        continue;
-      }
-    }
-    const double a2 = (double)nq * (8.0 * db.nnz + 8.0 * (db.n + 1) + 8.0 * (double)db.v_used * KT + 4.0 * db.n);
-    if ((rc = prof_begin(c, "phase2", a2))) return rc;
-    unsigned long long* p2c;
-    if ((rc = wsget(c, "p2_counters", 16, p2c))) return rc;
-    // whole 64-query groups word-major where that pays, the rest (and every
-    // group otherwise) per document; both give the same bits
-    const int64_t ng = !c->arena.base && use_word_major(c, db, KT) ? nq / 64 : 0;
-    if (ng > 0) {
-      float* cost;
-      if ((rc = wsget(c, "p2_cost", (size_t)db.nnz * 64, cost))) return rc;
-      for (int64_t g = 0; g < ng; ++g)
-        HIPCHK(c, launch_phase2_wordmajor(db.xptr, db.n, db.wptr, db.wwt, db.winv, db.nnz, db.v_used,
-                                          ZW + 2 * 64 * g, a.zw_nq, KT, cost, out + (q0 + 64 * g) * ld, ld, p2c,
-                                          c->stream));
-    }
-    if (nq > 64 * ng)
-      HIPCHK(c, launch_phase2_persistent(db.xptr, db.xcv, db.n, db.perm, ZW + 2 * 64 * ng, a.zw_nq, KT, nq - 64 * ng,
-                                         nullptr, out + (q0 + 64 * ng) * ld, ld, p2c, c->stream));
-    if ((rc = prof_end(c))) return rc;
+  if ((rc = wsget(c, "ovf_tiles", (size_t)Q.B, ovf))) return rc;
+  HIPCHK(c, launch_zero_ints(ovf, (int)Q.B, c->stream));
+  std::vector<std::pair<int64_t, int64_t>> tiles;
+  for (int64_t q0 = 0; q0 < Q.B;) {
+    const int64_t nq = std::min<int64_t>(d2q_tile_queries(c, db, KT0), Q.B - q0);
+    if ((rc = d2q_tile(c, db, Q, o, q0, nq, o->precision, full0, KT0, ovf + tiles.size(), out, ld))) return rc;
+    tiles.emplace_back(q0, nq);
     q0 += nq;
-    prec = o->precision;
+  }
+  std::vector<int> hf(tiles.size());
+  HIPCHK(c, hipMemcpyAsync(hf.data(), ovf, sizeof(int) * hf.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (size_t t = 0; t < tiles.size(); ++t) {
+    if (!hf[t]) continue;
+    // a row needed more list entries than the kernel keeps: float32 keys
+    // first, then (float32 already, or its redo overflowed) full-depth
+    // lists; the deeper tables may split the tile
+    int prec = o->precision, KT = KT0;
+    bool full = full0;
+    auto deeper = [&]() {
+      ++c->fallbacks;
+      if (prec != LCEMD_FP32) {
+        prec = LCEMD_FP32;
+        return true;
+      }
+      if (!full || KT < Q.hmax) {
+        full = true;
+        KT = Q.hmax;
+        return true;
+      }
+      return false;
+    };
+    const int64_t t0 = tiles[t].first, t1 = t0 + tiles[t].second;
+    bool ok = deeper();
+    for (int64_t r0 = t0; ok && r0 < t1;) {
+      const int64_t nq = std::min<int64_t>(d2q_tile_queries(c, db, KT), t1 - r0);
+      int h_ovf = 0;
+      HIPCHK(c, launch_zero_ints(ovf, 1, c->stream));
+      if ((rc = d2q_tile(c, db, Q, o, r0, nq, prec, full, KT, ovf, out, ld))) return rc;
+      HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (h_ovf) ok = deeper();  // the same queries again, one step deeper
+      else r0 += nq;
+    }
+    if (!ok)
+      return fail(c, LCEMD_E_CAPACITY, "a table row of queries [%lld, %lld) is deeper than its lists at full depth",
+                  (long long)t0, (long long)t1);
   }
   return LCEMD_OK;
 }
@@ -700,12 +737,23 @@ int lcemd_create(lcemd_ctx** out, int device) {
     return LCEMD_E_HIP;
   }
   c->stream = c->own_stream;
+  if (hipMalloc((void**)&c->fix_total, sizeof(unsigned long long)) != hipSuccess ||
+      hipMemsetAsync(c->fix_total, 0, sizeof(unsigned long long), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->fix_total) (void)hipFree(c->fix_total);
+    (void)hipStreamDestroy(c->own_stream);
+    delete c;
+    g_create_error = "device allocation of the context's counters failed";
+    return LCEMD_E_OOM;
+  }
   // the allocation-free scratch region of this device (looked up once per
   // device, with the device current); a failure only disables that call
   c->scratch_rc = noalloc_setup(device, &c->scratch);
   if (const char* fk = getenv("LCEMD_FORCE_KERNEL")) c->force_kernel = atoi(fk);
   if (const char* sc = getenv("LCEMD_SYM_CANDIDATES")) c->sym_candidates = atoi(sc);
   if (const char* p2 = getenv("LCEMD_PHASE2")) c->p2_mode = atoi(p2);
+  if (const char* tb = getenv("LCEMD_TABLE_BUDGET")) c->table_budget = (size_t)strtoull(tb, nullptr, 10);
   *out = c;
   return LCEMD_OK;
 }
@@ -718,6 +766,7 @@ void lcemd_destroy(lcemd_ctx* c) {
   free_db(c);
   free_emb(c);
   for (auto& kv : c->ws) dfree(kv.second.p);
+  dfree((void*&)c->fix_total);
   c->ws.clear();
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
@@ -937,7 +986,14 @@ int lcemd_profile(lcemd_ctx* c, int enable) {
 int lcemd_counters(lcemd_ctx* c, int64_t* fallback_tiles, int64_t* exact_rows) {
   if (!c) return LCEMD_E_INVALID_ARG;
   if (fallback_tiles) *fallback_tiles = c->fallbacks;
-  if (exact_rows) *exact_rows = c->fixed_rows;
+  if (exact_rows) {
+    unsigned long long t = 0;
+    if (c->fix_total) {
+      HIPCHK(c, hipMemcpyAsync(&t, c->fix_total, sizeof t, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    *exact_rows = (int64_t)t;
+  }
   return LCEMD_OK;
 }
 
@@ -1192,6 +1248,7 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
   a.overflow = ovf;
   a.fix_count = fixc;
   a.fix_cap = kFixCap;
+  a.fix_total = c->fix_total;
   if ((rc = p1_launch(c, a, P1_TABLE_FULL, o->precision, o->k, Q.hmax, Q.hmax))) return rc;
   {
     int h_ovf = 0, h_fix = 0;
@@ -1213,7 +1270,6 @@ int lcemd_tables(lcemd_ctx* c, const lcemd_query* q, const lcemd_opts* o, int32_
     }
     if (h_fix > 0) {
       HIPCHK(c, launch_fix_rows(a, P1_TABLE_FULL, h_fix, c->stream));
-      c->fixed_rows += h_fix;
       HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
       if (h_ovf) return fail(c, LCEMD_E_CAPACITY, "tables: rows need more candidates than the kernels keep");

@@ -70,12 +70,12 @@ struct lcemd_ctx {
   std::vector<int64_t> xptr_host;  // database row pointers (host copy)
   // scratch, grow-only
   std::map<std::string, DevBuf> ws;
-  size_t table_budget = size_t(12) << 30;
+  size_t table_budget = size_t(12) << 30;  // test hook LCEMD_TABLE_BUDGET (bytes) sets it at creation
   int force_kernel = 0;   // test hook (LCEMD_FORCE_KERNEL): 1 = skip the 128-row kernel, 2 = deep kernel
   int sym_candidates = 0; // test hook (LCEMD_SYM_CANDIDATES): first candidate count of the SYM top-l
   int p2_mode = 0;        // test hook (LCEMD_PHASE2): 0 = by table size, 1 = word-major when possible, 2 = per document
   int64_t fallbacks = 0;  // tiles redone with float32 keys / deeper lists
-  int64_t fixed_rows = 0; // bf16 table rows redone exactly one by one
+  unsigned long long* fix_total = nullptr;  // device: table rows redone exactly one by one
   // allocation-free calls: this device's scratch region and the arena over it
   void* scratch = nullptr;
   int scratch_rc = 0;

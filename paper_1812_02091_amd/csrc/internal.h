@@ -108,6 +108,7 @@ struct P1Args {
   int* fix_count;         // bf16 table modes: rows whose exactness certificate failed ...
   int64_t* fix_list;      // ... are appended here (flat table row index) for k_fix_rows
   int fix_cap;
+  unsigned long long* fix_total;  // optional: k_fix_rows adds the rows it redoes
   // persistent kernels: eight work counters (one per XCD), zeroed by the
   // launcher on its stream before the kernel
   unsigned long long* work_ctr;

@@ -879,6 +879,7 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
   __shared__ uint64_t taken[kThreads / 64][kTake];
   const int count = min(*a.fix_count, a.fix_cap);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (a.fix_total && blockIdx.x == 0 && threadIdx.x == 0 && count > 0) atomicAdd(a.fix_total, (unsigned long long)count);
   const int nw = gridDim.x * (kThreads / 64);
   uint64_t* tk = taken[wv];
   for (int item = blockIdx.x * (kThreads / 64) + wv; item < count; item += nw) {

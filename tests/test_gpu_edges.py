@@ -255,3 +255,39 @@ def test_batch_lanes_with_unaligned_rows_and_short_tail(L):
             part = ctx.distances(s.rowptr, s.col, s.val, method=method, k=k, direction="d2q")
             assert np.array_equal(part, g[b0:b0 + size]), (method, b0, size)
             b0 += size
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_deep_ict_rows_redo_their_tile(L, prec, monkeypatch):
+    """ICT rows deeper than any list the table kernels keep (Lemma 1: a word
+    of weight 1 in a database histogram needs every entry of a long, flat
+    query) overflow their tile, which is run again with float32 keys and
+    then full-depth lists.  A small table budget (test hook) splits the batch
+    into tiles of two queries, so only the middle tile overflows and its
+    rerun is split again; every distance still matches the oracle."""
+    rng = np.random.default_rng(31)
+    nv, m = 600, 32
+    V = rng.standard_normal((nv, m)).astype(np.float32)
+    rows = [([w], [1.0]) for w in range(10)]  # single-word histograms: capacity 1
+    for _ in range(30):
+        c = np.sort(rng.choice(nv, size=int(rng.integers(5, 21)), replace=False))
+        rows.append((c, rng.uniform(0.5, 2.0, size=len(c))))
+    db = _csr(rows)
+    qrows = []
+    for h in (5, 7, 200, 300, 6, 4):
+        c = np.sort(rng.choice(nv, size=h, replace=False))
+        qrows.append((c, rng.uniform(0.9, 1.1, size=h)))
+    q = _csr(qrows)
+    monkeypatch.setenv("LCEMD_TABLE_BUDGET", str(700 * 1024))
+    ctx = L.open_context(V, db.rowptr, db.col, db.val, precisions=("bf16",))
+    monkeypatch.delenv("LCEMD_TABLE_BUDGET")
+    orc = O.Oracle(V, db.rowptr, db.col, db.val)
+    fb0, _ = ctx.counters()
+    for d in ("d2q", "sym"):
+        say(f"[gpu] deep ICT rows {prec} {d}")
+        g = ctx.distances(q.rowptr, q.col, q.val, method="ict", k=1, direction=d, precision=prec)
+        P.assert_distances(g, orc.matrix(q.rowptr, q.col, q.val, "ict", 1, d), f"ict {prec} {d}")
+    fb1, fixed = ctx.counters()
+    assert fb1 > fb0, "no tile was redone"
+    assert fixed >= 0
+    ctx.close()
