@@ -134,7 +134,12 @@ int lcemd_version(void);
 /* Create a context on HIP device `device` (its own default-priority stream
  * until lcemd_set_stream).  *out receives the context.  Errors:
  * LCEMD_E_NO_DEVICE if the device does not exist or is not gfx950,
- * LCEMD_E_INVALID_ARG if out is NULL. */
+ * LCEMD_E_INVALID_ARG if out is NULL, LCEMD_E_OOM if its 8-byte device
+ * counter cannot be allocated.  Test hooks, read from the environment here:
+ * LCEMD_FORCE_KERNEL (1: skip the 128-row phase-1 kernel, 2: deep kernel),
+ * LCEMD_SYM_CANDIDATES (first candidate count of the symmetric top-l),
+ * LCEMD_PHASE2 (1: word-major phase 2 where possible, 2: per document),
+ * LCEMD_TABLE_BUDGET (bytes of phase-1 tables per tile; default 12 GiB). */
 int lcemd_create(lcemd_ctx** out, int device);
 
 /* Free all library-owned device memory and the context.  NULL-safe. */
