@@ -139,7 +139,9 @@ int lcemd_version(void);
  * LCEMD_FORCE_KERNEL (1: skip the 128-row phase-1 kernel, 2: deep kernel),
  * LCEMD_SYM_CANDIDATES (first candidate count of the symmetric top-l),
  * LCEMD_PHASE2 (1: word-major phase 2 where possible, 2: per document),
- * LCEMD_TABLE_BUDGET (bytes of phase-1 tables per tile; default 12 GiB). */
+ * LCEMD_TABLE_BUDGET (bytes of phase-1 tables per tile; default 12 GiB),
+ * LCEMD_FIX_CAP (rows per table tile that may be redone exactly; a tile
+ * with more uncertified rows is run again with float32 keys). */
 int lcemd_create(lcemd_ctx** out, int device);
 
 /* Free all library-owned device memory and the context.  NULL-safe. */

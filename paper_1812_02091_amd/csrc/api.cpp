@@ -456,15 +456,15 @@ int64_t d2q_tile_queries(lcemd_ctx* c, const DbView& db, int KT) {
   return Bt;
 }
 
-// One table tile, queries [q0, q0 + nq): phase 1 (Alg. 2-3 tables), the
-// exact redo of the rows it could not certify, and phase 2 (Eq. (6)-(9))
-// into out.  Nothing is read back: a row deeper than the lists raises *ovf
-// on the device, and the caller then runs the tile again.
-int d2q_tile(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, int64_t q0, int64_t nq,
-             int prec, bool full_lists, int KT, int* ovf, float* out, int64_t ld) {
+// Phase 1 (Alg. 2-3 tables) of queries [q0, q0 + nq) into *ZW, with the
+// exact redo of the rows it could not certify.  Nothing is read back: a row
+// deeper than the lists raises *ovf on the device.
+int d2q_tables(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, int64_t q0, int64_t nq,
+               int prec, bool full_lists, int KT, int* ovf, float2** ZWout) {
   int rc;
   float2* ZW;
   if ((rc = wsget(c, "zw", (size_t)zw_pitch(nq) * db.v_used * 2 * zw_pairs(KT), ZW))) return rc;
+  *ZWout = ZW;
   P1Args a = base_args(c, db, Q, o);
   a.qnnz = Q.nnz;
   a.KT = KT;
@@ -477,7 +477,8 @@ int d2q_tile(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o,
   // exact redo (every precision on the 128-row kernel); the redo kernel
   // reads the listed count on the device
   int* fixc = nullptr;
-  const int fixcap = c->arena.base ? kFixCapNoAlloc : kFixCap;
+  int fixcap = c->arena.base ? kFixCapNoAlloc : kFixCap;
+  if (c->fix_cap > 0) fixcap = std::min(fixcap, c->fix_cap);
   if ((rc = wsget(c, "fix_count", 1, fixc)) || (rc = wsget(c, "fix_list", fixcap, a.fix_list))) return rc;
   HIPCHK(c, launch_zero_ints(fixc, 1, c->stream));
   a.fix_count = fixc;
@@ -491,6 +492,14 @@ int d2q_tile(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o,
   if ((rc = prof_begin(c, "fix_rows", 0.0))) return rc;
   HIPCHK(c, launch_fix_rows(a, P1_TABLE, kFixGrid, c->stream));
   if ((rc = prof_end(c))) return rc;
+  return LCEMD_OK;
+}
+
+// Phase 2 (Eq. (6)-(9)) of queries [q0, q0 + nq) from their tables into out.
+int d2q_phase2(lcemd_ctx* c, const DbView& db, int64_t q0, int64_t nq, int KT, const float2* ZW, float* out,
+               int64_t ld) {
+  int rc;
+  const int64_t zw_nq = zw_pitch(nq);
   const double a2 = (double)nq * (8.0 * db.nnz + 8.0 * (db.n + 1) + 8.0 * (double)db.v_used * KT + 4.0 * db.n);
   if ((rc = prof_begin(c, "phase2", a2))) return rc;
   unsigned long long* p2c;
@@ -503,37 +512,90 @@ int d2q_tile(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o,
     if ((rc = wsget(c, "p2_cost", (size_t)db.nnz * 64, cost))) return rc;
     for (int64_t g = 0; g < ng; ++g)
       HIPCHK(c, launch_phase2_wordmajor(db.xptr, db.n, db.wptr, db.wwt, db.winv, db.nnz, db.v_used,
-                                        ZW + 2 * 64 * g, a.zw_nq, KT, cost, out + (q0 + 64 * g) * ld, ld, p2c,
+                                        ZW + 2 * 64 * g, zw_nq, KT, cost, out + (q0 + 64 * g) * ld, ld, p2c,
                                         c->stream));
   }
   if (nq > 64 * ng)
-    HIPCHK(c, launch_phase2_persistent(db.xptr, db.xcv, db.n, db.perm, ZW + 2 * 64 * ng, a.zw_nq, KT, nq - 64 * ng,
+    HIPCHK(c, launch_phase2_persistent(db.xptr, db.xcv, db.n, db.perm, ZW + 2 * 64 * ng, zw_nq, KT, nq - 64 * ng,
                                        nullptr, out + (q0 + 64 * ng) * ld, ld, p2c, c->stream));
   if ((rc = prof_end(c))) return rc;
   return LCEMD_OK;
 }
 
+// The list settings of a table tile, made one step deeper after an overflow:
+// float32 keys first, then (float32 already) full-depth lists.
+struct TileDepth {
+  int prec, KT;
+  bool full;
+  bool deeper(lcemd_ctx* c, int hmax) {
+    ++c->fallbacks;
+    if (prec != LCEMD_FP32) {
+      prec = LCEMD_FP32;
+      return true;
+    }
+    if (!full || KT < hmax) {
+      full = true;
+      KT = hmax;
+      return true;
+    }
+    return false;
+  }
+};
+
+// Queries [t0, t1) tile by tile, each tile's overflow flag read back before
+// its phase 2; a tile that overflowed is run again one step deeper (the
+// deeper tables may split it).
+int d2q_checked(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, int64_t t0, int64_t t1,
+                TileDepth d, int* ovf, float* out, int64_t ld) {
+  int rc;
+  for (int64_t r0 = t0; r0 < t1;) {
+    const int64_t nq = std::min<int64_t>(d2q_tile_queries(c, db, d.KT), t1 - r0);
+    float2* ZW;
+    int h_ovf = 0;
+    HIPCHK(c, launch_zero_ints(ovf, 1, c->stream));
+    if ((rc = d2q_tables(c, db, Q, o, r0, nq, d.prec, d.full, d.KT, ovf, &ZW))) return rc;
+    HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h_ovf) {  // the same queries again, one step deeper
+      if (!d.deeper(c, Q.hmax))
+        return fail(c, LCEMD_E_CAPACITY, "a table row of queries [%lld, %lld) is deeper than its lists at full depth",
+                    (long long)r0, (long long)(r0 + nq));
+      continue;
+    }
+    if ((rc = d2q_phase2(c, db, r0, nq, d.KT, ZW, out, ld))) return rc;
+    r0 += nq;
+  }
+  return LCEMD_OK;
+}
+
 // D2Q distances of every query against every row of `db` (Sec. 4):
-// out[b * ld + u].  The tiles run back to back, each with its own overflow
-// flag; the flags are read once, after the last tile, and a tile that
-// overflowed is run again with float32 keys, then (ICT) with full-depth
-// lists.  Phase 2 of an overflowed tile reads incomplete tables, but its
-// loops are bounded by the list depth, and the rerun overwrites its rows.
+// out[b * ld + u].  ICT's short lists overflow often, so its tiles are
+// checked one by one before their phase 2.  For the other measures, where
+// an overflow is rare, the tiles run back to back, each with its own
+// overflow flag; the flags are read once, after the last tile, and a tile
+// that overflowed is run again, checked, one step deeper.  Phase 2 of an
+// overflowed tile reads incomplete tables, but its loops are bounded by the
+// list depth and the database records, and the rerun rewrites its rows.
 int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, float* out, int64_t ld) {
-  const int KT0 = table_depth(o, Q.hmax);
   // ICT: the tables hold up to KT entries per row, but the lists of phase 1
   // stop at kIctList (a row needs a few entries before its capacities cover
   // the word's largest weight, Lemma 1); deeper rows are redone exactly
-  const bool full0 = o->method != LCEMD_ICT;
+  const TileDepth d0{o->precision, table_depth(o, Q.hmax), o->method != LCEMD_ICT};
   if (Q.B < 1) return LCEMD_OK;
   int* ovf;
   int rc;
+  if (o->method == LCEMD_ICT) {
+    if ((rc = wsget(c, "ovf", 1, ovf))) return rc;
+    return d2q_checked(c, db, Q, o, 0, Q.B, d0, ovf, out, ld);
+  }
   if ((rc = wsget(c, "ovf_tiles", (size_t)Q.B, ovf))) return rc;
   HIPCHK(c, launch_zero_ints(ovf, (int)Q.B, c->stream));
   std::vector<std::pair<int64_t, int64_t>> tiles;
   for (int64_t q0 = 0; q0 < Q.B;) {
-    const int64_t nq = std::min<int64_t>(d2q_tile_queries(c, db, KT0), Q.B - q0);
-    if ((rc = d2q_tile(c, db, Q, o, q0, nq, o->precision, full0, KT0, ovf + tiles.size(), out, ld))) return rc;
+    const int64_t nq = std::min<int64_t>(d2q_tile_queries(c, db, d0.KT), Q.B - q0);
+    float2* ZW;
+    if ((rc = d2q_tables(c, db, Q, o, q0, nq, d0.prec, d0.full, d0.KT, ovf + tiles.size(), &ZW))) return rc;
+    if ((rc = d2q_phase2(c, db, q0, nq, d0.KT, ZW, out, ld))) return rc;
     tiles.emplace_back(q0, nq);
     q0 += nq;
   }
@@ -542,39 +604,11 @@ int run_d2q(lcemd_ctx* c, const DbView& db, const QDev& Q, const lcemd_opts* o, 
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (size_t t = 0; t < tiles.size(); ++t) {
     if (!hf[t]) continue;
-    // a row needed more list entries than the kernel keeps: float32 keys
-    // first, then (float32 already, or its redo overflowed) full-depth
-    // lists; the deeper tables may split the tile
-    int prec = o->precision, KT = KT0;
-    bool full = full0;
-    auto deeper = [&]() {
-      ++c->fallbacks;
-      if (prec != LCEMD_FP32) {
-        prec = LCEMD_FP32;
-        return true;
-      }
-      if (!full || KT < Q.hmax) {
-        full = true;
-        KT = Q.hmax;
-        return true;
-      }
-      return false;
-    };
-    const int64_t t0 = tiles[t].first, t1 = t0 + tiles[t].second;
-    bool ok = deeper();
-    for (int64_t r0 = t0; ok && r0 < t1;) {
-      const int64_t nq = std::min<int64_t>(d2q_tile_queries(c, db, KT), t1 - r0);
-      int h_ovf = 0;
-      HIPCHK(c, launch_zero_ints(ovf, 1, c->stream));
-      if ((rc = d2q_tile(c, db, Q, o, r0, nq, prec, full, KT, ovf, out, ld))) return rc;
-      HIPCHK(c, hipMemcpyAsync(&h_ovf, ovf, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      if (h_ovf) ok = deeper();  // the same queries again, one step deeper
-      else r0 += nq;
-    }
-    if (!ok)
+    TileDepth d = d0;
+    if (!d.deeper(c, Q.hmax))
       return fail(c, LCEMD_E_CAPACITY, "a table row of queries [%lld, %lld) is deeper than its lists at full depth",
-                  (long long)t0, (long long)t1);
+                  (long long)tiles[t].first, (long long)(tiles[t].first + tiles[t].second));
+    if ((rc = d2q_checked(c, db, Q, o, tiles[t].first, tiles[t].first + tiles[t].second, d, ovf, out, ld))) return rc;
   }
   return LCEMD_OK;
 }
@@ -754,6 +788,7 @@ int lcemd_create(lcemd_ctx** out, int device) {
   if (const char* sc = getenv("LCEMD_SYM_CANDIDATES")) c->sym_candidates = atoi(sc);
   if (const char* p2 = getenv("LCEMD_PHASE2")) c->p2_mode = atoi(p2);
   if (const char* tb = getenv("LCEMD_TABLE_BUDGET")) c->table_budget = (size_t)strtoull(tb, nullptr, 10);
+  if (const char* fc = getenv("LCEMD_FIX_CAP")) c->fix_cap = atoi(fc);
   *out = c;
   return LCEMD_OK;
 }

@@ -74,6 +74,7 @@ struct lcemd_ctx {
   int force_kernel = 0;   // test hook (LCEMD_FORCE_KERNEL): 1 = skip the 128-row kernel, 2 = deep kernel
   int sym_candidates = 0; // test hook (LCEMD_SYM_CANDIDATES): first candidate count of the SYM top-l
   int p2_mode = 0;        // test hook (LCEMD_PHASE2): 0 = by table size, 1 = word-major when possible, 2 = per document
+  int fix_cap = 0;        // test hook (LCEMD_FIX_CAP): rows per table tile that may be redone exactly (0 = default)
   int64_t fallbacks = 0;  // tiles redone with float32 keys / deeper lists
   unsigned long long* fix_total = nullptr;  // device: table rows redone exactly one by one
   // allocation-free calls: this device's scratch region and the arena over it

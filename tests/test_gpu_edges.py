@@ -291,3 +291,48 @@ def test_deep_ict_rows_redo_their_tile(L, prec, monkeypatch):
     assert fb1 > fb0, "no tile was redone"
     assert fixed >= 0
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_overflowed_tiles_are_redone_after_the_pass(L, prec, monkeypatch):
+    """ACT table tiles run back to back and their overflow flags are read
+    once, after the last tile.  A query of 20 near-identical words (closer
+    than the bf16 keys resolve) fills every row's 16-entry list with ties, so
+    every row goes to the exact redo; a redo capacity of one row per tile
+    (test hook) then makes each tile holding such a query overflow, and
+    tiles of two queries (test hook) put those tiles beside clean ones
+    (one-word queries).  The flagged tiles are run again deeper, and every
+    distance and top-5 list matches the oracle."""
+    rng = np.random.default_rng(32)
+    nv, m = 500, 64
+    V = rng.standard_normal((nv, m)).astype(np.float32)
+    V[1:20] = V[0] + 1e-3 * rng.standard_normal((19, m)).astype(np.float32)
+    rows = []
+    for _ in range(60):
+        c = np.sort(rng.choice(np.arange(20, nv), size=int(rng.integers(10, 31)), replace=False))
+        rows.append((c, rng.uniform(0.5, 2.0, size=len(c))))
+    db = _csr(rows)
+    used = np.unique(db.col)
+    dup = (np.arange(20), rng.uniform(0.5, 1.5, size=20))
+    qrows = [dup if i % 3 == 0 else ([int(rng.integers(20, nv))], [1.0]) for i in range(6)]
+    q = _csr(qrows)
+    monkeypatch.setenv("LCEMD_TABLE_BUDGET", str(2 * len(used) * 16 + 8))
+    monkeypatch.setenv("LCEMD_FIX_CAP", "1")
+    ctx = L.open_context(V, db.rowptr, db.col, db.val, precisions=("bf16",))
+    monkeypatch.delenv("LCEMD_TABLE_BUDGET")
+    monkeypatch.delenv("LCEMD_FIX_CAP")
+    orc = O.Oracle(V, db.rowptr, db.col, db.val)
+    fb0, _ = ctx.counters()
+    for d in ("d2q", "sym"):
+        say(f"[gpu] overflowed tiles {prec} {d}")
+        o = orc.matrix(q.rowptr, q.col, q.val, "act", 2, d)
+        g = ctx.distances(q.rowptr, q.col, q.val, method="act", k=2, direction=d, precision=prec)
+        P.assert_distances(g, o, f"act {prec} {d}")
+        idx, dist = ctx.topl(q.rowptr, q.col, q.val, 5, method="act", k=2, direction=d, precision=prec)
+        for b in range(q.rowptr.size - 1):
+            P.check_topl(idx[b], dist[b], o[b], 5, f"act {prec} {d} query {b}")
+    fb1, _ = ctx.counters()
+    say(f"[gpu] overflowed tiles {prec}: {fb1 - fb0} tile redos")
+    if prec == "bf16":
+        assert fb1 > fb0, "no tile was redone"
+    ctx.close()
