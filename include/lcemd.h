@@ -141,7 +141,9 @@ int lcemd_version(void);
  * LCEMD_PHASE2 (1: word-major phase 2 where possible, 2: per document),
  * LCEMD_TABLE_BUDGET (bytes of phase-1 tables per tile; default 12 GiB),
  * LCEMD_FIX_CAP (rows per table tile that may be redone exactly; a tile
- * with more uncertified rows is run again with float32 keys). */
+ * with more uncertified rows is run again with float32 keys),
+ * LCEMD_SCRATCH_FAIL (scratch allocations granted before the next one is
+ * refused with LCEMD_E_OOM, as if the device were out of memory). */
 int lcemd_create(lcemd_ctx** out, int device);
 
 /* Free all library-owned device memory and the context.  NULL-safe. */

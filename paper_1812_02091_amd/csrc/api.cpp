@@ -789,6 +789,7 @@ int lcemd_create(lcemd_ctx** out, int device) {
   if (const char* p2 = getenv("LCEMD_PHASE2")) c->p2_mode = atoi(p2);
   if (const char* tb = getenv("LCEMD_TABLE_BUDGET")) c->table_budget = (size_t)strtoull(tb, nullptr, 10);
   if (const char* fc = getenv("LCEMD_FIX_CAP")) c->fix_cap = atoi(fc);
+  if (const char* sf = getenv("LCEMD_SCRATCH_FAIL")) c->ws_fail_after = atoll(sf);
   *out = c;
   return LCEMD_OK;
 }

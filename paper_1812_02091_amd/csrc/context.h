@@ -75,6 +75,8 @@ struct lcemd_ctx {
   int sym_candidates = 0; // test hook (LCEMD_SYM_CANDIDATES): first candidate count of the SYM top-l
   int p2_mode = 0;        // test hook (LCEMD_PHASE2): 0 = by table size, 1 = word-major when possible, 2 = per document
   int fix_cap = 0;        // test hook (LCEMD_FIX_CAP): rows per table tile that may be redone exactly (0 = default)
+  int64_t ws_fail_after = -1;  // test hook (LCEMD_SCRATCH_FAIL): scratch allocations granted before one is refused
+  int64_t ws_allocs = 0;       // scratch allocations made (counted for that hook)
   int64_t fallbacks = 0;  // tiles redone with float32 keys / deeper lists
   unsigned long long* fix_total = nullptr;  // device: table rows redone exactly one by one
   // allocation-free calls: this device's scratch region and the arena over it
@@ -145,6 +147,8 @@ int wsget(lcemd_ctx* c, const char* name, size_t count, T*& out) {
       b.p = nullptr;
       b.bytes = 0;
     }
+    if (c->ws_fail_after >= 0 && c->ws_allocs++ >= c->ws_fail_after)
+      return fail(c, LCEMD_E_OOM, "scratch allocation of %zu bytes (%s) refused (LCEMD_SCRATCH_FAIL)", bytes, name);
     if (hipMalloc(&b.p, bytes) != hipSuccess) {
       (void)hipGetLastError();
       return fail(c, LCEMD_E_OOM, "scratch allocation of %zu bytes (%s) failed", bytes, name);

@@ -336,3 +336,34 @@ def test_overflowed_tiles_are_redone_after_the_pass(L, prec, monkeypatch):
     if prec == "bf16":
         assert fb1 > fb0, "no tile was redone"
     ctx.close()
+
+
+@pytest.mark.parametrize("after", [0, 2, 4])
+def test_refused_scratch_allocation_is_reported(L, after, monkeypatch):
+    """A device allocation that fails inside a call (forced from the host:
+    the test hook refuses the context's scratch allocation number `after`)
+    ends the call with LCEMD_E_OOM and a message naming the buffer, leaves
+    the context closable, and a context without the hook computes the same
+    call correctly."""
+    rng = np.random.default_rng(33)
+    V = rng.standard_normal((300, 24)).astype(np.float32)
+    rows = []
+    for _ in range(40):
+        c = np.sort(rng.choice(300, size=int(rng.integers(3, 12)), replace=False))
+        rows.append((c, rng.uniform(0.5, 2.0, size=len(c))))
+    db = _csr(rows)
+    q = _csr(rows[:5])
+    monkeypatch.setenv("LCEMD_SCRATCH_FAIL", str(after))
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    monkeypatch.delenv("LCEMD_SCRATCH_FAIL")
+    say(f"[gpu] refused scratch allocation {after}")
+    with pytest.raises(L.LcemdError) as ei:
+        ctx.topl(q.rowptr, q.col, q.val, 3, method="act", k=2, direction="sym")
+    assert ei.value.code == L.E_OOM and "refused" in str(ei.value), str(ei.value)
+    ctx.close()
+    ctx = L.open_context(V, db.rowptr, db.col, db.val)
+    idx, dist = ctx.topl(q.rowptr, q.col, q.val, 3, method="act", k=2, direction="sym")
+    o = O.Oracle(V, db.rowptr, db.col, db.val).matrix(q.rowptr, q.col, q.val, "act", 2, "sym")
+    for b in range(5):
+        P.check_topl(idx[b], dist[b], o[b], 3, f"after refused scratch, query {b}")
+    ctx.close()
