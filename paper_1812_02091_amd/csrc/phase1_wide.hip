@@ -897,14 +897,28 @@ __global__ __launch_bounds__(kThreads) void k_fix_rows(P1Args a, const int64_t* 
       if (c < h) {
         const float4* q = (const float4*)(a.V + (size_t)a.qcol[s0 + c] * a.m_pad);
         float d2 = 0.f;
-        for (int d = 0; d < a.m4; ++d) {  // the zero padding adds exact zeros
-          const float4 y = q[d];
-          const float4 x = *(const float4*)(vrow + 4 * d);
-          float e;
-          e = x.x - y.x; d2 = fmaf(e, e, d2);
-          e = x.y - y.y; d2 = fmaf(e, e, d2);
-          e = x.z - y.z; d2 = fmaf(e, e, d2);
-          e = x.w - y.w; d2 = fmaf(e, e, d2);
+        // eight float4 of each vector (one 128-byte line) are loaded together
+        // and then added in the same order as one at a time (indices past
+        // the end are clamped and their values unused); the zero padding
+        // adds exact zeros
+        for (int d0 = 0; d0 < a.m4; d0 += 8) {
+          float4 y[8], x[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int d = min(d0 + i, a.m4 - 1);
+            y[i] = q[d];
+            x[i] = *(const float4*)(vrow + 4 * d);
+          }
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            if (d0 + i < a.m4) {
+              float e;
+              e = x[i].x - y[i].x; d2 = fmaf(e, e, d2);
+              e = x[i].y - y[i].y; d2 = fmaf(e, e, d2);
+              e = x[i].z - y[i].z; d2 = fmaf(e, e, d2);
+              e = x[i].w - y[i].w; d2 = fmaf(e, e, d2);
+            }
+          }
         }
         key[j] = w_pack(d2, (uint32_t)c);
       }
